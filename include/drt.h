@@ -1,0 +1,186 @@
+/*
+ * drt.h -- C ABI of the dynamic-ray-tracing (DRT) hot path on one AMD Instinct MI355X.
+ *
+ * Dynamic Ray Tracing (Bilibashi, Vitucci, Degli-Esposti, "On Dynamic Ray Tracing and
+ * Anticipative Channel Prediction for Dynamic Environments") takes the multipath of one
+ * ray-tracing snapshot at t0 and extrapolates every ray analytically over future instants
+ * t0 + dt while terminals and rigid bodies translate and rotate with constant velocity or
+ * acceleration (Sec. II).  This library keeps a scene resident in device memory and, per
+ * call, re-solves every ray's interaction points, its path length, delay, angles,
+ * Doppler and field coefficient at each instant, and synthesises the time-variant
+ * transfer function H(t, f) by summing the rays (Sec. II: "the total field, the
+ * time-variant channel's transfer function, Doppler's shift frequencies, time delays").
+ *
+ * Conventions
+ *   - every function returns an int status: DRT_OK (0) or a negative DRT_E_* code; on an
+ *     error the detail text is available from drt_last_error() in the calling thread and
+ *     out-parameters are left untouched;
+ *   - no C++ exception crosses this boundary;
+ *   - all host arrays passed in are borrowed for the duration of the call only (deep
+ *     copied); all device buffers passed in are caller-owned, never freed by the library;
+ *   - "device pointer" means memory allocated on the context's device (hipMalloc or a
+ *     PyTorch CUDA tensor); "stream" is a hipStream_t passed as void* (NULL = the null
+ *     stream); work is enqueued on it and the call returns without waiting;
+ *   - floats are IEEE binary64 unless stated; vectors are in metres in one global frame;
+ *     direction vectors must be unit length to 1e-9;
+ *   - all calls are thread-safe on one context.
+ */
+#ifndef DRT_H
+#define DRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct drt_ctx drt_ctx;
+
+enum drt_status {
+  DRT_OK = 0,
+  DRT_E_INVAL = -1,        /* bad argument, index out of range, malformed ray */
+  DRT_E_DEGENERATE = -2,   /* a ray is degenerate at t0 (see drt_load_scene) */
+  DRT_E_NOMEM = -3,        /* device allocation failed or the HBM cap would be exceeded */
+  DRT_E_ADMISSION = -4,    /* a request's footprint exceeds the HBM admission cap */
+  DRT_E_NOTFOUND = -5,     /* unknown scene id or ticket */
+  DRT_E_BUSY = -6,         /* scene still referenced by requests in flight */
+  DRT_E_DEVICE = -7,       /* a HIP runtime call failed */
+  DRT_E_INCONSISTENT = -8  /* ray_q0 disagrees with the t0 solve by more than 1e-6 m */
+};
+
+/* Arithmetic of a call.  DRT_FP64: everything in binary64, gains and H complex128.
+ * DRT_SPLIT: geometry and gains in binary64, the per-sample phasor work of H in binary32
+ * after reducing the carrier phase f*L/c modulo one cycle in binary64; gains complex64
+ * and H complex64.  DRT_NAIVE32: geometry, gains, phase and H all in binary32 (for the
+ * precision sweep only). */
+enum drt_precision { DRT_FP64 = 0, DRT_SPLIT = 1, DRT_NAIVE32 = 2 };
+
+enum drt_kind { DRT_R = 1, DRT_D = 2, DRT_S = 3 };   /* reflection, diffraction, scattering */
+enum drt_pol { DRT_PERP = 0, DRT_PAR = 1 };          /* soft / TE, hard / TM */
+
+#define DRT_MAX_INT 4
+
+/* The dynamic environment database (Sec. II): geometry at t0 plus the rigid-body dynamics
+ * of every object and terminal, and the interaction sequence of each t0 ray. */
+typedef struct {
+  double t0;                                   /* snapshot time [s] (metadata) */
+  double tx_p[3], tx_v[3], tx_a[3];            /* eq. Taylor: position, velocity, acceleration */
+  double rx_p[3], rx_v[3], rx_a[3];
+  int32_t n_bodies;                            /* >= 1; body 0 is the static world */
+  const double *body_O0;                       /* [nb][3] reference point on the rotation axis */
+  const double *body_v0, *body_a;              /* [nb][3] translation velocity and acceleration */
+  const double *body_axis;                     /* [nb][3] fixed unit rotation axis k */
+  const double *body_w0, *body_wdot;           /* [nb] angular speed and acceleration about k */
+  int32_t n_mat;
+  const double *mat_eps_r, *mat_sigma;         /* [nm] relative permittivity, conductivity [S/m] */
+  const uint8_t *mat_pec;                      /* [nm] 1 = perfect conductor */
+  int32_t n_planes;
+  const int32_t *plane_body, *plane_mat;       /* [np] */
+  const double *plane_p0, *plane_n0;           /* [np][3] a point of the plane, unit normal */
+  int32_t n_edges;
+  const int32_t *edge_body;                    /* [ne] */
+  const double *edge_a0, *edge_e0;             /* [ne][3] a point of the edge line, unit direction */
+  const double *edge_t0, *edge_n0;             /* [ne][3] 0-face unit tangent (pointing away from the
+                                                  edge) and 0-face outward unit normal */
+  const double *edge_wedge_n;                  /* [ne] exterior wedge angle / pi */
+  int32_t n_tiles;
+  const int32_t *tile_body, *tile_alpha;       /* [nt] body, directive-lobe exponent 1..8 */
+  const uint8_t *tile_model;                   /* [nt] 0 Lambertian, 1 directive */
+  const double *tile_c0, *tile_n0;             /* [nt][3] centroid, outward unit normal */
+  const double *tile_area, *tile_S, *tile_phase0;  /* [nt] dS [m^2], scattering coefficient, phase */
+  int32_t n_rays;
+  const uint8_t *ray_nint;                     /* [nr] 0..4 interactions (0 = line of sight) */
+  const uint8_t *ray_kind, *ray_pol;           /* [nr][4] drt_kind, drt_pol per interaction */
+  const int32_t *ray_prim;                     /* [nr][4] index into planes / edges / tiles */
+  const double *ray_q0;                        /* optional [nr][4][3] t0 interaction points; NULL = skip */
+} drt_scene_desc;
+
+/* t_j = t0 + j*dt, j = 0..n_steps-1. */
+typedef struct { double dt; int32_t n_steps; } drt_time_grid;
+/* f_k = f_c + (k - n_sub/2) * bandwidth / n_sub (integer division), k = 0..n_sub-1. */
+typedef struct { double f_c, bandwidth; int32_t n_sub; } drt_freq_grid;
+
+/* Caller-owned device outputs of drt_extrapolate, each [n_rays][n_steps] (time fastest);
+ * any pointer may be NULL to skip that output.  gain is complex128 (interleaved re, im)
+ * for DRT_FP64 and complex64 otherwise.  An instant where the ray's chain is inconsistent
+ * (a reflection point outside the segment from its virtual receiver to its image, a
+ * diffraction source or receiver on the edge line, a tile facing away from a terminal)
+ * has valid = 0 and every other output 0; no NaN is ever written. */
+typedef struct {
+  double *L;                                   /* path length [m] */
+  float *dop;                                  /* Doppler shift at f_c [Hz], > 0 when approaching */
+  float *aod_az, *aod_el, *aoa_az, *aoa_el;    /* departure / arrival azimuth, elevation [rad] */
+  void *gain;                                  /* field coefficient at f_c (no propagation phase) */
+  uint8_t *valid;
+} drt_ray_out;
+
+typedef struct {
+  uint32_t scene;
+  int32_t n_rays;                              /* rays [0, n_rays) of the scene */
+  drt_time_grid tg;
+  drt_freq_grid fg;
+  int32_t precision;                           /* DRT_SPLIT or DRT_FP64 */
+  void *H;                                     /* device, [n_steps][n_sub] complex64 / complex128 */
+} drt_request;
+
+typedef struct {
+  int32_t state;                               /* 0 queued, 1 running, 2 done, < 0 error status */
+  double t_arrive, t_admit, t_done;            /* seconds on the library's monotonic clock */
+} drt_req_stat;
+
+/* Create a context on HIP device `device`.  hbm_cap_bytes bounds the device memory the
+ * context holds (resident scenes, scratch, in-flight requests); 0 = 90% of the device. */
+int drt_create(int device, uint64_t hbm_cap_bytes, drt_ctx **out);
+
+/* Destroy a context: waits for in-flight work, frees every scene and scratch buffer. */
+int drt_destroy(drt_ctx *ctx);
+
+/* Validate, pack and upload a scene (Sec. II's dynamic environment database plus the t0
+ * rays).  Errors: DRT_E_INVAL (index out of range, n_int > 4, more than one diffraction
+ * in a ray, a scattering interaction that is not the ray's only one, non-unit vectors);
+ * DRT_E_DEGENERATE (at t0 a reflection's image line is parallel to its wall, i.e. the
+ * denominator y_TX + y_RX of eq. ref_point vanishes, or a diffraction source/receiver
+ * lies on the edge line, d_TX + d_RX = 0 in eq. diff_point); DRT_E_INCONSISTENT (ray_q0
+ * given and farther than 1e-6 m from the t0 solve).  The scene stays resident until
+ * drt_unload_scene. */
+int drt_load_scene(drt_ctx *ctx, const drt_scene_desc *desc, uint32_t *scene_id);
+
+/* Free a scene.  DRT_E_BUSY while served requests still reference it. */
+int drt_unload_scene(drt_ctx *ctx, uint32_t scene_id);
+
+/* Per-(ray, instant) extrapolation (Sec. III: reflection points by image and
+ * back-tracking, diffraction points by the unfolded similar-triangle closed form,
+ * scattering points carried rigidly with their body; App. A Doppler) for rays
+ * [0, n_rays) over the time grid, field coefficients at carrier f_c.  Writes the
+ * non-NULL members of *out on `stream`. */
+int drt_extrapolate(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_grid *tg,
+                    double f_c, int32_t precision, const drt_ray_out *out, void *stream);
+
+/* Time-variant transfer function H[j][k] = sum_r a_r(t_j) exp(-j 2 pi f_k L_r(t_j) / c)
+ * for rays [0, n_rays), written to the device buffer H ([n_steps][n_sub], interleaved
+ * complex128 for DRT_FP64, complex64 otherwise) on `stream`.  Deterministic: the same
+ * inputs give bitwise the same H whatever else runs on the device. */
+int drt_cfr(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_grid *tg,
+            const drt_freq_grid *fg, int32_t precision, void *H, void *stream);
+
+/* Serving: enqueue one channel-prediction request (continuous batching on internal
+ * streams).  Non-blocking.  DRT_E_ADMISSION if its device footprint alone exceeds the
+ * cap; otherwise it waits in the queue until memory frees up.  req->H is borrowed until
+ * drt_poll reports done or an error. */
+int drt_submit(drt_ctx *ctx, const drt_request *req, uint64_t *ticket);
+
+/* Non-blocking status of a ticket; a ticket reported done or failed is forgotten
+ * afterwards (DRT_E_NOTFOUND on the next poll). */
+int drt_poll(drt_ctx *ctx, uint64_t ticket, drt_req_stat *stat);
+
+/* Seconds on the clock used by drt_req_stat. */
+double drt_now(void);
+
+const char *drt_strerror(int status);
+const char *drt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DRT_H */

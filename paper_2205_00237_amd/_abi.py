@@ -1,0 +1,233 @@
+"""ctypes binding of libdrt (include/drt.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Device buffers are
+passed as raw pointers (a PyTorch CUDA tensor's data_ptr()) and streams as hipStream_t
+handles (torch.cuda.current_stream().cuda_stream).  Importing this module loads the
+library built in-tree by paper_2205_00237_amd/build.py and fails loudly when it is missing.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdrt.so")
+
+DRT_OK = 0
+DRT_E_INVAL = -1
+DRT_E_DEGENERATE = -2
+DRT_E_NOMEM = -3
+DRT_E_ADMISSION = -4
+DRT_E_NOTFOUND = -5
+DRT_E_BUSY = -6
+DRT_E_DEVICE = -7
+DRT_E_INCONSISTENT = -8
+
+DRT_FP64, DRT_SPLIT, DRT_NAIVE32 = 0, 1, 2
+
+EXPORTS = ("drt_create", "drt_destroy", "drt_load_scene", "drt_unload_scene", "drt_extrapolate",
+           "drt_cfr", "drt_submit", "drt_poll", "drt_now", "drt_strerror", "drt_last_error")
+
+_dp = C.POINTER(C.c_double)
+_u8p = C.POINTER(C.c_uint8)
+_i32p = C.POINTER(C.c_int32)
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [
+        ("t0", C.c_double),
+        ("tx_p", C.c_double * 3), ("tx_v", C.c_double * 3), ("tx_a", C.c_double * 3),
+        ("rx_p", C.c_double * 3), ("rx_v", C.c_double * 3), ("rx_a", C.c_double * 3),
+        ("n_bodies", C.c_int32),
+        ("body_O0", _dp), ("body_v0", _dp), ("body_a", _dp), ("body_axis", _dp),
+        ("body_w0", _dp), ("body_wdot", _dp),
+        ("n_mat", C.c_int32),
+        ("mat_eps_r", _dp), ("mat_sigma", _dp), ("mat_pec", _u8p),
+        ("n_planes", C.c_int32),
+        ("plane_body", _i32p), ("plane_mat", _i32p), ("plane_p0", _dp), ("plane_n0", _dp),
+        ("n_edges", C.c_int32),
+        ("edge_body", _i32p), ("edge_a0", _dp), ("edge_e0", _dp), ("edge_t0", _dp), ("edge_n0", _dp),
+        ("edge_wedge_n", _dp),
+        ("n_tiles", C.c_int32),
+        ("tile_body", _i32p), ("tile_alpha", _i32p), ("tile_model", _u8p),
+        ("tile_c0", _dp), ("tile_n0", _dp), ("tile_area", _dp), ("tile_S", _dp), ("tile_phase0", _dp),
+        ("n_rays", C.c_int32),
+        ("ray_nint", _u8p), ("ray_kind", _u8p), ("ray_pol", _u8p), ("ray_prim", _i32p),
+        ("ray_q0", _dp),
+    ]
+
+
+class TimeGrid(C.Structure):
+    _fields_ = [("dt", C.c_double), ("n_steps", C.c_int32)]
+
+
+class FreqGrid(C.Structure):
+    _fields_ = [("f_c", C.c_double), ("bandwidth", C.c_double), ("n_sub", C.c_int32)]
+
+
+class RayOut(C.Structure):
+    _fields_ = [("L", C.c_void_p), ("dop", C.c_void_p), ("aod_az", C.c_void_p), ("aod_el", C.c_void_p),
+                ("aoa_az", C.c_void_p), ("aoa_el", C.c_void_p), ("gain", C.c_void_p), ("valid", C.c_void_p)]
+
+
+class Request(C.Structure):
+    _fields_ = [("scene", C.c_uint32), ("n_rays", C.c_int32), ("tg", TimeGrid), ("fg", FreqGrid),
+                ("precision", C.c_int32), ("H", C.c_void_p)]
+
+
+class ReqStat(C.Structure):
+    _fields_ = [("state", C.c_int32), ("t_arrive", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+
+class DrtError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {LIB.drt_strerror(status).decode()} ({status}): "
+                         f"{LIB.drt_last_error().decode()}")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libdrt.so not found at {LIB_PATH}: run paper_2205_00237_amd.build.build() "
+                          "(or __graft_entry__.build()) first; there is no fallback path")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    sig = {
+        "drt_create": (C.c_int, [C.c_int, C.c_uint64, C.POINTER(vp)]),
+        "drt_destroy": (C.c_int, [vp]),
+        "drt_load_scene": (C.c_int, [vp, C.POINTER(SceneDesc), C.POINTER(C.c_uint32)]),
+        "drt_unload_scene": (C.c_int, [vp, C.c_uint32]),
+        "drt_extrapolate": (C.c_int, [vp, C.c_uint32, C.c_int32, C.POINTER(TimeGrid), C.c_double,
+                                      C.c_int32, C.POINTER(RayOut), vp]),
+        "drt_cfr": (C.c_int, [vp, C.c_uint32, C.c_int32, C.POINTER(TimeGrid), C.POINTER(FreqGrid),
+                              C.c_int32, vp, vp]),
+        "drt_submit": (C.c_int, [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+        "drt_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(ReqStat)]),
+        "drt_now": (C.c_double, []),
+        "drt_strerror": (C.c_char_p, [C.c_int]),
+        "drt_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def _check(status, where):
+    if status != DRT_OK:
+        raise DrtError(status, where)
+
+
+def _arr(a, dtype, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def scene_desc(scene, ray_q0=None):
+    """Build a drt_scene_desc over numpy copies of a scene dictionary.  Returns (desc, keep)
+    where `keep` holds the arrays that the pointers reference."""
+    keep = {}
+
+    def p(key, dtype, ctype):
+        a = _arr(scene[key], dtype)
+        keep[key] = a
+        return a.ctypes.data_as(C.POINTER(ctype)) if a.size else C.POINTER(ctype)()
+
+    d = SceneDesc()
+    d.t0 = float(scene.get("t0", 0.0))
+    for k in ("tx_p", "tx_v", "tx_a", "rx_p", "rx_v", "rx_a"):
+        setattr(d, k, (C.c_double * 3)(*[float(x) for x in np.asarray(scene[k]).reshape(3)]))
+    d.n_bodies = int(np.asarray(scene["body_w0"]).shape[0])
+    for k in ("body_O0", "body_v0", "body_a", "body_axis", "body_w0", "body_wdot"):
+        setattr(d, k, p(k, np.float64, C.c_double))
+    d.n_mat = int(np.asarray(scene["mat_eps_r"]).shape[0])
+    d.mat_eps_r = p("mat_eps_r", np.float64, C.c_double)
+    d.mat_sigma = p("mat_sigma", np.float64, C.c_double)
+    d.mat_pec = p("mat_pec", np.uint8, C.c_uint8)
+    d.n_planes = int(np.asarray(scene["plane_body"]).shape[0])
+    d.plane_body = p("plane_body", np.int32, C.c_int32)
+    d.plane_mat = p("plane_mat", np.int32, C.c_int32)
+    d.plane_p0 = p("plane_p0", np.float64, C.c_double)
+    d.plane_n0 = p("plane_n0", np.float64, C.c_double)
+    d.n_edges = int(np.asarray(scene["edge_body"]).shape[0])
+    d.edge_body = p("edge_body", np.int32, C.c_int32)
+    for k in ("edge_a0", "edge_e0", "edge_t0", "edge_n0", "edge_wedge_n"):
+        setattr(d, k, p(k, np.float64, C.c_double))
+    d.n_tiles = int(np.asarray(scene["tile_body"]).shape[0])
+    d.tile_body = p("tile_body", np.int32, C.c_int32)
+    d.tile_alpha = p("tile_alpha", np.int32, C.c_int32)
+    d.tile_model = p("tile_model", np.uint8, C.c_uint8)
+    for k in ("tile_c0", "tile_n0", "tile_area", "tile_S", "tile_phase0"):
+        setattr(d, k, p(k, np.float64, C.c_double))
+    d.n_rays = int(np.asarray(scene["ray_nint"]).shape[0])
+    d.ray_nint = p("ray_nint", np.uint8, C.c_uint8)
+    d.ray_kind = p("ray_kind", np.uint8, C.c_uint8)
+    d.ray_pol = p("ray_pol", np.uint8, C.c_uint8)
+    d.ray_prim = p("ray_prim", np.int32, C.c_int32)
+    if ray_q0 is not None:
+        q = _arr(ray_q0, np.float64, (d.n_rays, 4, 3))
+        keep["ray_q0"] = q
+        d.ray_q0 = q.ctypes.data_as(_dp)
+    return d, keep
+
+
+# ----------------------------------------------------------------------------- C names
+
+def drt_create(device=0, hbm_cap_bytes=0):
+    ctx = C.c_void_p()
+    _check(LIB.drt_create(int(device), int(hbm_cap_bytes), C.byref(ctx)), "drt_create")
+    return ctx
+
+
+def drt_destroy(ctx):
+    _check(LIB.drt_destroy(ctx), "drt_destroy")
+
+
+def drt_load_scene(ctx, scene, ray_q0=None):
+    d, keep = scene_desc(scene, ray_q0)
+    sid = C.c_uint32()
+    _check(LIB.drt_load_scene(ctx, C.byref(d), C.byref(sid)), "drt_load_scene")
+    return sid.value
+
+
+def drt_unload_scene(ctx, sid):
+    _check(LIB.drt_unload_scene(ctx, int(sid)), "drt_unload_scene")
+
+
+def drt_extrapolate(ctx, sid, n_rays, dt, n_steps, f_c, precision, out_ptrs, stream=0):
+    """out_ptrs: dict with any of L, dop, aod_az, aod_el, aoa_az, aoa_el, gain, valid -> device pointer."""
+    tg = TimeGrid(float(dt), int(n_steps))
+    o = RayOut(**{k: int(v) for k, v in out_ptrs.items() if v})
+    _check(LIB.drt_extrapolate(ctx, int(sid), int(n_rays), C.byref(tg), float(f_c), int(precision),
+                               C.byref(o), C.c_void_p(int(stream))), "drt_extrapolate")
+
+
+def drt_cfr(ctx, sid, n_rays, dt, n_steps, f_c, bandwidth, n_sub, precision, H_ptr, stream=0):
+    tg = TimeGrid(float(dt), int(n_steps))
+    fg = FreqGrid(float(f_c), float(bandwidth), int(n_sub))
+    _check(LIB.drt_cfr(ctx, int(sid), int(n_rays), C.byref(tg), C.byref(fg), int(precision),
+                       C.c_void_p(int(H_ptr)), C.c_void_p(int(stream))), "drt_cfr")
+
+
+def drt_submit(ctx, sid, n_rays, dt, n_steps, f_c, bandwidth, n_sub, precision, H_ptr):
+    r = Request(int(sid), int(n_rays), TimeGrid(float(dt), int(n_steps)),
+                FreqGrid(float(f_c), float(bandwidth), int(n_sub)), int(precision), C.c_void_p(int(H_ptr)))
+    t = C.c_uint64()
+    _check(LIB.drt_submit(ctx, C.byref(r), C.byref(t)), "drt_submit")
+    return t.value
+
+
+def drt_poll(ctx, ticket):
+    st = ReqStat()
+    _check(LIB.drt_poll(ctx, int(ticket), C.byref(st)), "drt_poll")
+    return st.state, st.t_arrive, st.t_admit, st.t_done
+
+
+def drt_now():
+    return LIB.drt_now()

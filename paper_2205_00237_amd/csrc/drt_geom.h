@@ -1,0 +1,492 @@
+// Per-(ray, instant) DRT geometry and field coefficient, templated on the real type.
+//
+// Shared by the gfx950 kernels (one lane per (ray, instant)) and by the host loader's t0
+// checks.  Everything is written in the global frame: a rigidly carried point is
+// O(t) + R(t)(X0 - O0) with R(t) the rotation by theta(t) = w0*dt + wdot*dt^2/2 about the
+// body's fixed axis (Sec. III-A.1; eq. coordinate_transf), which is algebraically the
+// paper's local-frame procedure without the explicit change of frame.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "drt_layout.h"
+
+namespace drt {
+
+#define DRT_HD __host__ __device__ __forceinline__
+
+DRT_HD double msqrt(double x) { return ::sqrt(x); }
+DRT_HD float msqrt(float x) { return ::sqrtf(x); }
+DRT_HD double mfloor(double x) { return ::floor(x); }
+DRT_HD float mfloor(float x) { return ::floorf(x); }
+DRT_HD double matan2(double y, double x) { return ::atan2(y, x); }
+DRT_HD float matan2(float y, float x) { return ::atan2f(y, x); }
+DRT_HD double mtan(double x) { return ::tan(x); }
+DRT_HD float mtan(float x) { return ::tanf(x); }
+DRT_HD double mcos(double x) { return ::cos(x); }
+DRT_HD float mcos(float x) { return ::cosf(x); }
+DRT_HD double msin(double x) { return ::sin(x); }
+DRT_HD float msin(float x) { return ::sinf(x); }
+DRT_HD double mrint(double x) { return ::rint(x); }
+DRT_HD float mrint(float x) { return ::rintf(x); }
+DRT_HD double mfabs(double x) { return ::fabs(x); }
+DRT_HD float mfabs(float x) { return ::fabsf(x); }
+DRT_HD bool mfinite(double x) { return isfinite(x); }
+DRT_HD bool mfinite(float x) { return isfinite(x); }
+
+template <class F> struct V3 { F x, y, z; };
+template <class F> DRT_HD V3<F> v3(F x, F y, F z) { return V3<F>{x, y, z}; }
+template <class F> DRT_HD V3<F> ld3(const double* p) { return V3<F>{F(p[0]), F(p[1]), F(p[2])}; }
+template <class F> DRT_HD V3<F> operator+(V3<F> a, V3<F> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class F> DRT_HD V3<F> operator-(V3<F> a, V3<F> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class F> DRT_HD V3<F> operator-(V3<F> a) { return {-a.x, -a.y, -a.z}; }
+template <class F> DRT_HD V3<F> operator*(F s, V3<F> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <class F> DRT_HD F dot(V3<F> a, V3<F> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class F> DRT_HD V3<F> cross(V3<F> a, V3<F> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <class F> DRT_HD F norm(V3<F> a) { return msqrt(dot(a, a)); }
+
+template <class F> struct Cx { F re, im; };
+template <class F> DRT_HD Cx<F> cx(F r, F i) { return Cx<F>{r, i}; }
+template <class F> DRT_HD Cx<F> operator+(Cx<F> a, Cx<F> b) { return {a.re + b.re, a.im + b.im}; }
+template <class F> DRT_HD Cx<F> operator-(Cx<F> a, Cx<F> b) { return {a.re - b.re, a.im - b.im}; }
+template <class F> DRT_HD Cx<F> operator*(Cx<F> a, Cx<F> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class F> DRT_HD Cx<F> operator*(F s, Cx<F> a) { return {s * a.re, s * a.im}; }
+template <class F> DRT_HD Cx<F> cdiv(Cx<F> a, Cx<F> b) {
+  F d = F(1) / (b.re * b.re + b.im * b.im);
+  return {(a.re * b.re + a.im * b.im) * d, (a.im * b.re - a.re * b.im) * d};
+}
+// principal square root (non-negative real part)
+template <class F> DRT_HD Cx<F> csqrt(Cx<F> w) {
+  F r = msqrt(w.re * w.re + w.im * w.im);
+  if (r == F(0)) return {F(0), F(0)};
+  F t = msqrt((r + mfabs(w.re)) * F(0.5));
+  if (w.re >= F(0)) return {t, w.im / (F(2) * t)};
+  return {mfabs(w.im) / (F(2) * t), w.im >= F(0) ? t : -t};
+}
+
+template <class F> struct Consts {
+  static constexpr F pi = F(3.14159265358979323846);
+  static constexpr F c0 = F(299792458.0);
+};
+
+// ---------------------------------------------------------------------------------------
+// rigid-body pose of one body at one instant
+
+template <class F> struct Pose {
+  V3<F> O, O0, V, k;
+  F W, s, c1;       // angular speed, sin(theta), 1 - cos(theta)
+  bool moving;
+};
+
+template <class F>
+DRT_HD Pose<F> make_pose(const DBody& b, F dt, F sin_th, F one_minus_cos) {
+  Pose<F> p;
+  p.O0 = ld3<F>(b.O0);
+  p.k = ld3<F>(b.k);
+  V3<F> v0 = ld3<F>(b.v0), a = ld3<F>(b.a);
+  p.O = p.O0 + dt * v0 + (F(0.5) * dt * dt) * a;
+  p.V = v0 + dt * a;
+  p.W = F(b.w0) + F(b.wdot) * dt;
+  p.s = sin_th;
+  p.c1 = one_minus_cos;
+  p.moving = b.moving != 0;
+  return p;
+}
+
+template <class F> DRT_HD V3<F> rot(const Pose<F>& p, V3<F> v) {
+  V3<F> kv = cross(p.k, v);
+  return v + p.s * kv + p.c1 * cross(p.k, kv);
+}
+template <class F> DRT_HD V3<F> place(const Pose<F>& p, V3<F> x0) {
+  return p.moving ? p.O + rot(p, x0 - p.O0) : x0;
+}
+template <class F> DRT_HD V3<F> carry(const Pose<F>& p, V3<F> d0) { return p.moving ? rot(p, d0) : d0; }
+template <class F> DRT_HD V3<F> material_velocity(const Pose<F>& p, V3<F> x) {
+  if (!p.moving) return v3<F>(0, 0, 0);
+  return p.V + p.W * cross(p.k, x - p.O);
+}
+
+// ---------------------------------------------------------------------------------------
+// one interaction slot moved to the instant
+
+template <class F> struct Slot {
+  V3<F> p, n;        // plane point / edge point / tile centroid; normal (plane, tile, 0-face)
+  V3<F> e, t;        // edge direction, 0-face tangent
+  Pose<F> pose;
+};
+
+template <class F> DRT_HD V3<F> mirror(V3<F> x, V3<F> p, V3<F> n) {
+  return x - (F(2) * dot(x - p, n)) * n;
+}
+
+// Reflection points from src to dst over M walls w[0..M): images forward, then
+// back-tracking from dst; ok &= every parameter s in (0, 1).
+template <class F, int M>
+DRT_HD void reflect_chain(V3<F> src, V3<F> dst, const Slot<F>* w, V3<F>* Q, bool& ok, bool& degen) {
+  if constexpr (M > 0) {
+    V3<F> A[M];
+    V3<F> a = src;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      a = mirror(a, w[m].p, w[m].n);
+      A[m] = a;
+    }
+    V3<F> nxt = dst;
+#pragma unroll
+    for (int m = M - 1; m >= 0; --m) {
+      F num = dot(nxt - w[m].p, w[m].n);
+      F den = dot(nxt - A[m], w[m].n);
+      F s = num / den;
+      bool fin = mfinite(s);
+      degen = degen || !fin;
+      ok = ok && fin && s > F(0) && s < F(1);
+      if (!fin) s = F(0);
+      Q[m] = nxt + s * (A[m] - nxt);
+      nxt = Q[m];
+    }
+  }
+}
+
+constexpr double kRhoMin = 1e-9;    // diffraction source/receiver this close to the edge: degenerate
+constexpr double kUtdEpsD = 1e-8;   // shadow-boundary switch of cot*F (binary64)
+constexpr float kUtdEpsF = 1e-4f;   // same, binary32
+
+template <class F> struct ChainOut {
+  V3<F> Q[DRT_MAX_INT];
+  V3<F> A, B;         // unfolded image source / receiver of the diffraction
+  F rhoA, rhoB;
+  bool ok, degen;
+};
+
+// Interaction points of an N-interaction chain with its diffraction at slot DP (DP < 0:
+// reflections only).  Sec. III-A.2 (images and back-tracking), Sec. III-B (eq. diff_point).
+template <class F, int N, int DP>
+DRT_HD void solve_points(V3<F> TX, V3<F> RX, const Slot<F>* sl, ChainOut<F>& c) {
+  c.ok = true;
+  c.degen = false;
+  if constexpr (DP < 0) {
+    reflect_chain<F, N>(TX, RX, sl, c.Q, c.ok, c.degen);
+  } else {
+    V3<F> A = TX;
+#pragma unroll
+    for (int i = 0; i < DP; ++i) A = mirror(A, sl[i].p, sl[i].n);
+    V3<F> B = RX;
+#pragma unroll
+    for (int i = N - 1; i > DP; --i) B = mirror(B, sl[i].p, sl[i].n);
+    const Slot<F>& ed = sl[DP];
+    F zA = dot(A - ed.p, ed.e), zB = dot(B - ed.p, ed.e);
+    F rA = norm((A - ed.p) - zA * ed.e), rB = norm((B - ed.p) - zB * ed.e);
+    F zQ = zB + rB * (zA - zB) / (rA + rB);
+    if (!mfinite(zQ)) zQ = F(0);
+    V3<F> QD = ed.p + zQ * ed.e;
+    c.Q[DP] = QD;
+    reflect_chain<F, DP>(TX, QD, sl, c.Q, c.ok, c.degen);
+    reflect_chain<F, N - DP - 1>(QD, RX, sl + DP + 1, c.Q + DP + 1, c.ok, c.degen);
+    bool far = rA > F(kRhoMin) && rB > F(kRhoMin);
+    c.ok = c.ok && far;
+    c.degen = c.degen || !far;
+    c.A = A;
+    c.B = B;
+    c.rhoA = rA;
+    c.rhoB = rB;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// field coefficients (Fresnel, UTD, Effective Roughness)
+
+template <class F>
+DRT_HD Cx<F> fresnel(F cos_t, const DMat& m, F lam, int pol) {
+  if (m.pec) return cx<F>(pol == DRT_PAR ? F(1) : F(-1), F(0));
+  Cx<F> eps = cx<F>(F(m.eps_r), -F(60) * F(m.sigma) * lam);
+  Cx<F> root = csqrt(cx<F>(eps.re - (F(1) - cos_t * cos_t), eps.im));
+  if (pol == DRT_PAR) {
+    Cx<F> ec = cos_t * eps;
+    return cdiv(ec - root, ec + root);
+  }
+  return cdiv(cx<F>(cos_t, F(0)) - root, cx<F>(cos_t, F(0)) + root);
+}
+
+// UTD transition function F(X) = 2j sqrt(X) e^{jX} int_{sqrt X}^inf e^{-j tau^2} d tau.
+// Small X: power series of the Fresnel integral from 0 to sqrt(X).  Larger X: the
+// tail is (sqrt(pi)/2) e^{-j pi/4} erfc(e^{j pi/4} sqrt X) and the even continued fraction
+// of erfc gives F(X) = jX / t with t = z2 + 1/2 - (1*2/4)/(z2 + 5/2 - (3*4/4)/(z2 + 9/2 ...)),
+// z2 = jX, evaluated backwards from a fixed depth.
+template <class F> struct FxParams;
+template <> struct FxParams<double> { static constexpr double xs = 4.5; static constexpr int ns = 36, depth = 32; };
+template <> struct FxParams<float> { static constexpr float xs = 4.0f; static constexpr int ns = 22, depth = 14; };
+
+template <class F> DRT_HD Cx<F> utd_transition(F X) {
+  if (X <= F(0)) return cx<F>(F(0), F(0));
+  if (X < FxParams<F>::xs) {
+    F x = msqrt(X);
+    F term = x, sr = F(0), si = F(0);
+#pragma unroll 4
+    for (int n = 0; n < FxParams<F>::ns; ++n) {
+      F v = term / F(2 * n + 1);
+      switch (n & 3) {         // (-j)^n
+        case 0: sr += v; break;
+        case 1: si -= v; break;
+        case 2: sr -= v; break;
+        default: si += v; break;
+      }
+      term = term * X / F(n + 1);
+    }
+    const F h = F(0.62665706865775012);      // sqrt(pi/8) = sqrt(pi)/2 * cos(pi/4)
+    Cx<F> tail = cx<F>(h - sr, -h - si);     // sqrt(pi)/2 e^{-j pi/4} - S
+    Cx<F> e = cx<F>(mcos(X), msin(X));
+    return (F(2) * x) * (cx<F>(F(0), F(1)) * (e * tail));
+  }
+  Cx<F> t = cx<F>(F(4 * FxParams<F>::depth + 1) * F(0.5), X);
+#pragma unroll 4
+  for (int n = FxParams<F>::depth; n >= 1; --n) {
+    F c = F((2 * n - 1) * (2 * n)) * F(0.25);
+    Cx<F> q = cdiv(cx<F>(c, F(0)), t);
+    t = cx<F>(F(4 * n - 3) * F(0.5) - q.re, X - q.im);
+  }
+  return cdiv(cx<F>(F(0), X), t);
+}
+
+template <class F> DRT_HD Cx<F> cot_F(F beta, F sgn, F n, F kL) {
+  const F pi = Consts<F>::pi;
+  F N = mrint((beta + sgn * pi) / (F(2) * pi * n));
+  F eps = pi + sgn * beta - sgn * F(2) * pi * n * N;
+  const F lim = sizeof(F) == 8 ? F(kUtdEpsD) : F(kUtdEpsF);
+  if (mfabs(eps) < lim) {
+    F sg = eps > F(0) ? F(1) : (eps < F(0) ? F(-1) : F(0));
+    const F r2 = F(0.70710678118654752);
+    Cx<F> w = cx<F>(r2, r2);                                // e^{j pi/4}
+    Cx<F> inner = cx<F>(msqrt(F(2) * pi * kL) * sg, F(0)) - (F(2) * kL * eps) * w;
+    return n * (inner * w);
+  }
+  F c = mcos((F(2) * n * pi * N - beta) * F(0.5));
+  F a = F(2) * c * c;
+  Cx<F> fx = utd_transition(kL * a);
+  F ct = F(1) / mtan((pi + sgn * beta) / (F(2) * n));
+  return ct * fx;
+}
+
+// Kouyoumjian-Pathak coefficient of a perfectly conducting wedge (soft for pol 0, hard for 1).
+template <class F> DRT_HD Cx<F> utd_coefficient(F phi, F phi_p, F sin_b0, F n, F k, F Ld, int pol) {
+  const F pi = Consts<F>::pi;
+  F bm = phi - phi_p, bp = phi + phi_p, kL = k * Ld;
+  Cx<F> tm = cot_F(bm, F(1), n, kL) + cot_F(bm, F(-1), n, kL);
+  Cx<F> tp = cot_F(bp, F(1), n, kL) + cot_F(bp, F(-1), n, kL);
+  Cx<F> sum = pol == DRT_PAR ? tm + tp : tm - tp;
+  const F r2 = F(0.70710678118654752);
+  F scale = F(1) / (F(2) * n * msqrt(F(2) * pi * k) * sin_b0);
+  Cx<F> pre = cx<F>(-r2 * scale, r2 * scale);                // -e^{-j pi/4} * scale
+  return pre * sum;
+}
+
+// integral over the scattering hemisphere of ((1 + cos psi_R)/2)^alpha, integer alpha
+template <class F> DRT_HD F er_norm_directive(int alpha, F cos_ti) {
+  const F pi = Consts<F>::pi;
+  F sin2 = F(1) - cos_ti * cos_ti;
+  F total = F(0), binom = F(1);    // C(alpha, j)
+  for (int j = 0; j <= alpha; ++j) {
+    F Ij;
+    if ((j & 1) == 0) {
+      Ij = F(2) * pi / F(j + 1);
+    } else {
+      F acc = F(0), cw = F(1), pw = F(1);   // C(2w, w) / 4^w and sin2^w
+      for (int w = 0; w <= (j - 1) / 2; ++w) {
+        acc += cw * pw;
+        cw = cw * F((2 * w + 1) * (2 * w + 2)) / F((w + 1) * (w + 1)) * F(0.25);
+        pw *= sin2;
+      }
+      Ij = F(2) * pi / F(j + 1) * cos_ti * acc;
+    }
+    total += binom * Ij;
+    binom = binom * F(alpha - j) / F(j + 1);
+  }
+  F scale = F(1);
+  for (int j = 0; j < alpha; ++j) scale *= F(0.5);
+  return total * scale;
+}
+
+// ---------------------------------------------------------------------------------------
+// the whole per-(ray, instant) evaluation
+
+template <class F> struct RayResult {
+  F L, dop, aod_az, aod_el, aoa_az, aoa_el;
+  Cx<F> gain;
+  bool ok, degen;
+  V3<F> Q[DRT_MAX_INT];      // interaction points (used by the loader's t0 checks)
+};
+
+template <class F> DRT_HD void dir_angles(V3<F> v, F& az, F& el) {
+  az = matan2(v.y, v.x);
+  el = matan2(v.z, msqrt(v.x * v.x + v.y * v.y));
+}
+
+// Evaluate one ray whose N interaction slots are already moved to the instant.
+// Template parameters fix the signature so that every array stays in registers.
+template <class F, int N, int DP, bool SCAT>
+DRT_HD RayResult<F> eval_ray(const SceneView& sc, const DRay& ray, const Slot<F>* sl, V3<F> TX,
+                             V3<F> VTX, V3<F> RX, V3<F> VRX, F f_c) {
+  const F pi = Consts<F>::pi;
+  RayResult<F> res;
+  ChainOut<F> ch;
+  if constexpr (SCAT) {
+    ch.ok = true;
+    ch.degen = false;
+    ch.Q[0] = sl[0].p;
+  } else {
+    solve_points<F, N, DP>(TX, RX, sl, ch);
+  }
+  V3<F> verts[N + 2];
+  verts[0] = TX;
+#pragma unroll
+  for (int i = 0; i < N; ++i) verts[i + 1] = ch.Q[i];
+  verts[N + 1] = RX;
+  V3<F> kh[N + 1];
+  F len[N + 1];
+  F L = F(0);
+#pragma unroll
+  for (int i = 0; i <= N; ++i) {
+    V3<F> d = verts[i + 1] - verts[i];
+    len[i] = norm(d);
+    kh[i] = (F(1) / len[i]) * d;
+    L += len[i];
+    ch.degen = ch.degen || !(len[i] > F(0));
+  }
+  // Doppler: f_D = -(f_c/c) sum_i k_i . (u_i - u_{i-1}), u the material velocities
+  V3<F> uprev = VTX;
+  F dLdt = F(0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    V3<F> u = material_velocity(sl[i].pose, ch.Q[i]);
+    dLdt += dot(kh[i], u - uprev);
+    uprev = u;
+  }
+  dLdt += dot(kh[N], VRX - uprev);
+  res.dop = -(f_c / Consts<F>::c0) * dLdt;
+  dir_angles(kh[0], res.aod_az, res.aod_el);
+  dir_angles(-kh[N], res.aoa_az, res.aoa_el);
+  res.L = L;
+
+  const F lam = Consts<F>::c0 / f_c;
+  Cx<F> gam = cx<F>(F(1), F(0));
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (SCAT || i == DP) continue;
+    const DPlane& pl = sc.planes[ray.prim[i]];
+    F ct = mfabs(dot(kh[i], sl[i].n));
+    gam = gam * fresnel<F>(ct, sc.mats[pl.mat], lam, ray.pol[i]);
+  }
+  bool ok = ch.ok;
+  Cx<F> a;
+  if constexpr (SCAT) {
+    const DTile& tl = sc.tiles[ray.prim[0]];
+    V3<F> n = sl[0].n;
+    F cti = -dot(kh[0], n), cts = dot(kh[1], n);
+    ok = ok && cti > F(0) && cts > F(0);
+    V3<F> spec = kh[0] - (F(2) * dot(kh[0], n)) * n;
+    F cpsi = dot(spec, kh[1]);
+    F amp;
+    F ci = ok ? cti : F(1), cs = ok ? cts : F(1);
+    if (tl.model == 0) {
+      amp = F(tl.S) * msqrt(F(tl.area) * ci * cs / pi);
+    } else {
+      F x = (F(1) + cpsi) * F(0.5);
+      if (x < F(0)) x = F(0);
+      F lobe = F(1);
+      for (int j = 0; j < tl.alpha / 2; ++j) lobe *= x;
+      if (tl.alpha & 1) lobe *= msqrt(x);
+      amp = F(tl.S) * msqrt(F(tl.area) * ci / er_norm_directive<F>(tl.alpha, ci)) * lobe;
+    }
+    F ph = F(tl.phase0);
+    F sc_ = lam / (F(4) * pi) * amp / (len[0] * len[1]);
+    a = cx<F>(sc_ * mcos(ph), sc_ * msin(ph));
+  } else if constexpr (DP >= 0) {
+    const DEdge& ed = sc.edges[ray.prim[DP]];
+    const Slot<F>& es = sl[DP];
+    V3<F> QD = ch.Q[DP];
+    V3<F> dA = ch.A - QD, dB = ch.B - QD;
+    F sp = norm(dA), s = norm(dB);
+    F cb = -dot(dA, es.e) / sp;
+    F sb2 = F(1) - cb * cb;
+    F sb = msqrt(sb2 > F(0) ? sb2 : F(0));
+    V3<F> up = dA - dot(dA, es.e) * es.e;
+    V3<F> uo = dB - dot(dB, es.e) * es.e;
+    F phi_p = matan2(dot(up, es.n), dot(up, es.t));
+    F phi = matan2(dot(uo, es.n), dot(uo, es.t));
+    if (phi_p < F(0)) phi_p += F(2) * pi;
+    if (phi < F(0)) phi += F(2) * pi;
+    F Ld = s * sp * sb * sb / (s + sp);
+    F k = F(2) * pi / lam;
+    Cx<F> D = utd_coefficient<F>(phi, phi_p, sb, F(ed.wn), k, Ld, ray.pol[DP]);
+    F scale = lam / (F(4) * pi) / msqrt(sp * s * (sp + s));
+    a = scale * (gam * D);
+  } else {
+    a = (lam / (F(4) * pi * L)) * gam;
+  }
+  if (!ok) {
+    res.L = res.dop = res.aod_az = res.aod_el = res.aoa_az = res.aoa_el = F(0);
+    a = cx<F>(F(0), F(0));
+  }
+  res.gain = a;
+  res.ok = ok;
+  res.degen = ch.degen;
+#pragma unroll
+  for (int i = 0; i < N; ++i) res.Q[i] = ch.Q[i];
+  return res;
+}
+
+// Move interaction slot i of `ray` to the instant (poses already evaluated per slot).
+template <class F>
+DRT_HD void load_slot(const SceneView& sc, int kind, int prim, const Pose<F>& pose, Slot<F>& s) {
+  s.pose = pose;
+  if (kind == DRT_R) {
+    const DPlane& p = sc.planes[prim];
+    s.p = place(pose, ld3<F>(p.p0));
+    s.n = carry(pose, ld3<F>(p.n0));
+  } else if (kind == DRT_D) {
+    const DEdge& e = sc.edges[prim];
+    s.p = place(pose, ld3<F>(e.a0));
+    s.e = carry(pose, ld3<F>(e.e0));
+    s.t = carry(pose, ld3<F>(e.t0));
+    s.n = carry(pose, ld3<F>(e.n0));
+  } else {
+    const DTile& t = sc.tiles[prim];
+    s.p = place(pose, ld3<F>(t.c0));
+    s.n = carry(pose, ld3<F>(t.n0));
+  }
+}
+
+DRT_HD int prim_body(const SceneView& sc, int kind, int prim) {
+  if (kind == DRT_R) return sc.planes[prim].body;
+  if (kind == DRT_D) return sc.edges[prim].body;
+  return sc.tiles[prim].body;
+}
+
+// Dispatch on the signature code (DRay::code) to the matching template instance.
+template <class F, class Fn> DRT_HD auto with_signature(int code, Fn&& fn) {
+  switch (code) {
+    case SIG_LOS: return fn.template operator()<0, -1, false>();
+    case SIG_R1: return fn.template operator()<1, -1, false>();
+    case SIG_R2: return fn.template operator()<2, -1, false>();
+    case SIG_R3: return fn.template operator()<3, -1, false>();
+    case SIG_R4: return fn.template operator()<4, -1, false>();
+    case SIG_D: return fn.template operator()<1, 0, false>();
+    case SIG_DR: return fn.template operator()<2, 0, false>();
+    case SIG_RD: return fn.template operator()<2, 1, false>();
+    case SIG_DRR: return fn.template operator()<3, 0, false>();
+    case SIG_RDR: return fn.template operator()<3, 1, false>();
+    case SIG_RRD: return fn.template operator()<3, 2, false>();
+    case SIG_DRRR: return fn.template operator()<4, 0, false>();
+    case SIG_RDRR: return fn.template operator()<4, 1, false>();
+    case SIG_RRDR: return fn.template operator()<4, 2, false>();
+    case SIG_RRRD: return fn.template operator()<4, 3, false>();
+    default: return fn.template operator()<1, -1, true>();
+  }
+}
+
+}  // namespace drt

@@ -1,0 +1,44 @@
+// Launchers of the gfx950 kernels (kernels.hip) used by the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "drt_layout.h"
+
+namespace drt {
+
+enum GeomMode { GEOM_EXTRAP = 0, GEOM_ANCHOR = 1 };
+
+constexpr int kNK = 16;          // subcarriers walked by one lane from its phase anchor
+constexpr int kMinSlice = 8;     // fewest rays per wave slice of the ray sum
+
+struct ExtrapOut {
+  double* L;
+  float *dop, *aod_az, *aod_el, *aoa_az, *aoa_el;
+  void* gain;
+  uint8_t* valid;
+};
+
+// Partition of H = sum over rays: a wave owns TTc instants x (KB * kNK) subcarriers of one
+// ray slice; a workgroup = 4 waves = 4 consecutive slices of one tile, summed in LDS; G
+// slice groups per tile are summed afterwards by k_reduce when G > 1.
+struct CfrArgs {
+  int n_rays, T, K;
+  int KB, TTc, nT, nK, G, slice_len, n_blocks;
+  double f0, df;
+};
+
+size_t pose_bytes(int nb, int T, int prec);
+size_t record_bytes(int n_rays, int T, int prec);
+CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_waves);
+
+hipError_t launch_pose(const DBody* bodies, int nb, int T, double dt, int prec, void* out, hipStream_t st);
+hipError_t launch_geom(const SceneView& sc, const void* pose, int T, double dt, double f_c, int n_rays, int prec,
+                       int mode, const ExtrapOut& eo, void* rec, double df_over_c, hipStream_t st);
+hipError_t launch_cfr(const void* rec, const CfrArgs& a, int prec, void* out, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_reduce(const void* part, int G, size_t n, int prec, void* H, hipStream_t st);
+
+}  // namespace drt

@@ -1,0 +1,67 @@
+// Device-resident layout of one scene: array-of-structs tables for the primitives (read
+// through the scalar cache: every wave works on one ray, so primitive indices are
+// wave-uniform) and a 32-byte record per ray.
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/drt.h"
+
+namespace drt {
+
+struct DBody {          // 128 B
+  double O0[3], v0[3], a[3], k[3];
+  double w0, wdot;
+  int32_t moving, pad0;
+  int32_t pad1[2];
+};
+struct DMat {           // 24 B
+  double eps_r, sigma;
+  int32_t pec, pad;
+};
+struct DPlane {         // 56 B
+  double p0[3], n0[3];
+  int32_t body, mat;
+};
+struct DEdge {          // 112 B
+  double a0[3], e0[3], t0[3], n0[3];
+  double wn;
+  int32_t body, pad;
+};
+struct DTile {          // 88 B
+  double c0[3], n0[3];
+  double area, S, phase0;
+  int32_t body, alpha, model, pad;
+};
+
+// interaction signature of a ray (at most one diffraction, scattering only alone)
+enum SigCode : uint8_t {
+  SIG_LOS = 0, SIG_R1, SIG_R2, SIG_R3, SIG_R4,
+  SIG_D, SIG_DR, SIG_RD, SIG_DRR, SIG_RDR, SIG_RRD, SIG_DRRR, SIG_RDRR, SIG_RRDR, SIG_RRRD,
+  SIG_S, SIG_COUNT
+};
+
+struct DRay {           // 48 B
+  uint8_t nint, code, dpos, pad;
+  uint8_t kind[4];
+  uint8_t pol[4];
+  int32_t prim[4];
+  int32_t body[4];      // body of each slot's primitive (0 for unused slots)
+  int32_t pad2;
+};
+static_assert(sizeof(DRay) == 48, "DRay layout");
+static_assert(sizeof(DBody) == 128, "DBody layout");
+
+struct SceneView {
+  const DBody* bodies;
+  const DMat* mats;
+  const DPlane* planes;
+  const DEdge* edges;
+  const DTile* tiles;
+  const DRay* rays;
+  double tx_p[3], tx_v[3], tx_a[3];
+  double rx_p[3], rx_v[3], rx_a[3];
+  int32_t n_bodies, n_rays;
+};
+
+}  // namespace drt

@@ -1,0 +1,81 @@
+"""CPU check of the field-coefficient functions of the kernels' shared header
+(paper_2205_00237_amd/csrc/drt_geom.h), compiled for the host, against the oracle."""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import em
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = "/opt/rocm/bin/hipcc"
+
+
+@pytest.fixture(scope="module")
+def probe(tmp_path_factory):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("probe") / "geom_probe")
+    cmd = [HIPCC, "-O2", "-std=c++20", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include",
+           "-I", os.path.join(ROOT, "paper_2205_00237_amd", "csrc"), "-x", "c++",
+           os.path.join(ROOT, "tests", "host", "geom_probe.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+    def run(lines):
+        out = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True, check=True)
+        return [list(map(float, l.split())) for l in out.stdout.strip().splitlines()]
+    return run
+
+
+def test_transition_function(probe):
+    X = np.concatenate([np.logspace(-9, 6, 300), [4.4999999, 4.5, 4.5000001, 4.0, 3.99999]])
+    got64 = probe([f"F64 {float(x)!r}" for x in X])
+    got32 = probe([f"F32 {float(x)!r}" for x in X])
+    ref = em.utd_transition(X)
+    for x, g, g32, r in zip(X, got64, got32, ref):
+        assert abs(complex(*g) - r) <= 1e-13 * abs(r) + 1e-300, (x, g, r)
+        assert abs(complex(*g32) - r) <= 3e-6 * abs(r), (x, g32, r)
+
+
+def test_wedge_coefficient(probe):
+    rng = np.random.default_rng(0)
+    lines, args = [], []
+    for _ in range(400):
+        n = rng.choice([1.5, 2.0, rng.uniform(1.1, 2.0)])
+        phi, php = rng.uniform(0, n * math.pi, 2)
+        sb, k, Ld, pol = rng.uniform(0.2, 1), rng.choice([125.7, 586.7, 1257.0]), rng.uniform(0.1, 300), int(rng.integers(2))
+        lines.append("D64 " + " ".join(repr(float(v)) for v in (phi, php, sb, n, k, Ld)) + f" {pol}")
+        args.append((phi, php, sb, n, k, Ld, pol))
+    # exactly on the incidence and reflection shadow boundaries (limit branch)
+    for pol in (0, 1):
+        for php in (0.3, 1.1):
+            for phi in (math.pi + php, math.pi - php):
+                lines.append(f"D64 {phi!r} {php!r} 1.0 1.5 586.7 12.0 {pol}")
+                args.append((phi, php, 1.0, 1.5, 586.7, 12.0, pol))
+    got = probe(lines)
+    for a, g in zip(args, got):
+        r = complex(em.utd_coefficient(*a))
+        assert abs(complex(*g) - r) <= 1e-11 * abs(r), (a, g, r)
+
+
+def test_fresnel_and_er_norm(probe):
+    rng = np.random.default_rng(1)
+    lines, refs = [], []
+    for _ in range(300):
+        ct, er, sg, lam = rng.uniform(0, 1), rng.uniform(1, 20), rng.uniform(0, 2), rng.uniform(0.001, 0.1)
+        pec, pol = int(rng.random() < 0.2), int(rng.integers(2))
+        lines.append("G64 " + " ".join(repr(float(v)) for v in (ct, er, sg, lam)) + f" {pec} {pol}")
+        refs.append(complex(em.fresnel_gamma(ct, er, sg, lam, bool(pec), pol)))
+    for g, r in zip(probe(lines), refs):
+        assert abs(complex(*g) - r) <= 1e-14, (g, r)
+    lines, refs = [], []
+    for alpha in range(0, 9):
+        for ct in np.linspace(0.01, 1, 23):
+            lines.append(f"ER64 {alpha} {float(ct)!r}")
+            refs.append(float(em.er_norm_directive(alpha, ct)))
+    for g, r in zip(probe(lines), refs):
+        assert abs(g[0] - r) <= 1e-14 * r

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Tolerances: binary64 mode |dL| <= 1e-9 m (path length), |dH| / rms(H) <= 1e-6, gains
+relative 1e-9, Doppler and angles within their binary32 output rounding; split mode
+|H| within 1e-4 relative and arg H within 1e-3 rad on every (t, f) where |H_ref| is at
+least 0.1 rms(|H_ref|) (a relative error is meaningless in deep fades), and
+|dH| / rms(H) <= 1e-4 everywhere."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2205_00237_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+C0 = 299_792_458.0
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_00237_amd.drt import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def h_errors(H, Href):
+    rms = np.sqrt(np.mean(np.abs(Href) ** 2))
+    m = np.abs(Href) >= 0.1 * rms
+    e_all = np.abs(H - Href).max() / rms
+    e_mag = (np.abs(np.abs(H[m]) - np.abs(Href[m])) / np.abs(Href[m])).max()
+    e_arg = np.abs(np.angle(H[m] * np.conj(Href[m]))).max()
+    return e_all, e_mag, e_arg
+
+
+def check_extrapolation(out, ref, prec, where):
+    from paper_2205_00237_amd.drt import DRT_FP64
+    v = out["valid"].cpu().numpy().astype(bool)
+    assert np.array_equal(v, ref["valid"]), f"{where}: valid flags differ at {np.argwhere(v != ref['valid'])[:5]}"
+    L = out["L"].cpu().numpy()
+    assert np.abs(L - ref["L"]).max() <= 1e-9, f"{where}: |dL| {np.abs(L - ref['L']).max()}"
+    dop = out["dop"].cpu().numpy().astype(np.float64)
+    tol_d = 1e-5 + np.abs(ref["dop"]) * 2.0 ** -23
+    assert (np.abs(dop - ref["dop"]) <= tol_d).all(), f"{where}: doppler {np.abs(dop - ref['dop']).max()}"
+    for k in ("aod_az", "aod_el", "aoa_az", "aoa_el"):
+        a = out[k].cpu().numpy().astype(np.float64)
+        d = np.abs(a - ref[k])
+        d = np.minimum(d, 2 * math.pi - d)   # +-pi azimuth wrap
+        assert (d <= 1e-9 + np.abs(ref[k]) * 2.0 ** -23).all(), f"{where}: {k} {d.max()}"
+    g = out["gain"].cpu().numpy().astype(np.complex128)
+    gr = ref["gain"]
+    scale = np.abs(gr).max()
+    rel = 1e-9 if prec == DRT_FP64 else 2.0 ** -23
+    assert (np.abs(g - gr) <= rel * np.abs(gr) + 1e-12 * scale).all(), \
+        f"{where}: gain {(np.abs(g - gr) / np.maximum(np.abs(gr), 1e-300)).max()}"
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config1_extrapolate_and_cfr(ctx, precision):
+    from paper_2205_00237_amd.drt import DRT_FP64
+    say(f"config1 extrapolate+cfr precision={precision}")
+    s, tg, fg = scenes.config1()
+    sid = ctx.load_scene(s)
+    ref, Href = oracle.run(s, tg, fg)
+    out = ctx.extrapolate(sid, tg, fg.f_c, precision)
+    check_extrapolation(out, ref, precision, "config1")
+    H = ctx.cfr(sid, tg, fg, precision).cpu().numpy()
+    e_all, e_mag, e_arg = h_errors(H.astype(np.complex128), Href)
+    say(f"  H errors: all {e_all:.3g} mag {e_mag:.3g} arg {e_arg:.3g}")
+    if precision == DRT_FP64:
+        assert e_all <= 1e-6
+    else:
+        assert e_all <= 1e-4 and e_mag <= 1e-4 and e_arg <= 1e-3
+    ctx.unload_scene(sid)
+
+
+@pytest.mark.parametrize("T,K,nr", [(1, 1, 1), (37, 50, 7), (65, 17, 25), (130, 64, 25), (64, 2048, 3)])
+def test_ragged_shapes(ctx, T, K, nr):
+    say(f"ragged T={T} K={K} n_rays={nr}")
+    s, _, fg0 = scenes.config1()
+    tg = scenes.TimeGrid(7e-4, T)
+    fg = scenes.FreqGrid(28e9, 100e6 * K / 64, K)
+    sid = ctx.load_scene(s)
+    ref, Href = oracle.run(s, tg, fg, rays=np.arange(nr))
+    for prec in (0, 1):
+        out = ctx.extrapolate(sid, tg, fg.f_c, prec, n_rays=nr)
+        check_extrapolation(out, ref, prec, f"ragged{T, K, nr}")
+        H = ctx.cfr(sid, tg, fg, prec, n_rays=nr).cpu().numpy().astype(np.complex128)
+        e_all, e_mag, e_arg = h_errors(H, Href)
+        assert e_all <= (1e-6 if prec == 0 else 1e-4), (prec, e_all)
+    ctx.unload_scene(sid)
+
+
+def test_empty_inputs(ctx):
+    say("empty inputs")
+    s, tg, fg = scenes.config1()
+    sid = ctx.load_scene(s)
+    H = torch.full((tg.n_steps, fg.n_sub), 7.0 + 1j, dtype=torch.complex64, device="cuda")
+    ctx.cfr(sid, tg, fg, 1, n_rays=0, out=H)
+    assert torch.count_nonzero(H).item() == 0
+    out = ctx.extrapolate(sid, scenes.TimeGrid(1e-3, 0), fg.f_c, 1)
+    assert out["L"].numel() == 0
+    ctx.unload_scene(sid)
+
+
+def test_config2_full_size(ctx):
+    """The urban workload at its full size, in the launch configuration the benchmark times:
+    geometry of every (ray, instant) in binary64, and H on sampled instants in both modes."""
+    say("config2 full size")
+    s, tg, fg = scenes.config2()
+    sid = ctx.load_scene(s)
+    rows = np.array([0, 1, 63, 64, 333, 517, 998, 999])
+    ref_rows, Href = oracle.run(s, tg, fg, t_index=rows)
+    out = ctx.extrapolate(sid, tg, fg.f_c, 0)
+    say("  oracle geometry at every instant ...")
+    ref = oracle.extrapolate(s, np.arange(tg.n_steps) * tg.dt, fg.f_c)
+    check_extrapolation(out, ref, 0, "config2")
+    for prec in (0, 1):
+        H = ctx.cfr(sid, tg, fg, prec).cpu().numpy().astype(np.complex128)[rows]
+        e_all, e_mag, e_arg = h_errors(H, Href)
+        say(f"  prec {prec}: H errors all {e_all:.3g} mag {e_mag:.3g} arg {e_arg:.3g}")
+        if prec == 0:
+            assert e_all <= 1e-6
+        else:
+            assert e_all <= 1e-4 and e_mag <= 1e-4 and e_arg <= 1e-3
+    ctx.unload_scene(sid)
+
+
+def test_config3_scattering(ctx):
+    """Scattering-heavy workload (reduced to 6 boxes x 500 tiles for the per-element check)
+    plus the full-size launch on sampled rows."""
+    say("config3 reduced")
+    s, tg, fg = scenes.config3(n_boxes=6, tiles_per_box=500, n_steps=150)
+    sid = ctx.load_scene(s)
+    ref, Href = oracle.run(s, tg, fg)
+    for prec in (0, 1):
+        out = ctx.extrapolate(sid, tg, fg.f_c, prec)
+        check_extrapolation(out, ref, prec, "config3")
+        H = ctx.cfr(sid, tg, fg, prec).cpu().numpy().astype(np.complex128)
+        e_all, e_mag, e_arg = h_errors(H, Href)
+        say(f"  prec {prec}: H errors all {e_all:.3g} mag {e_mag:.3g} arg {e_arg:.3g}")
+        assert e_all <= (1e-6 if prec == 0 else 1e-4)
+        if prec == 1:
+            assert e_mag <= 1e-4 and e_arg <= 1e-3
+    ctx.unload_scene(sid)
+
+
+def test_config3_full_size_sampled(ctx):
+    say("config3 full size sampled rows")
+    s, tg, fg = scenes.config3()
+    sid = ctx.load_scene(s)
+    rows = np.array([0, 255, 499])
+    _, Href = oracle.run(s, tg, fg, t_index=rows)
+    H = ctx.cfr(sid, tg, fg, 1).cpu().numpy().astype(np.complex128)[rows]
+    e_all, e_mag, e_arg = h_errors(H, Href)
+    say(f"  split: H errors all {e_all:.3g} mag {e_mag:.3g} arg {e_arg:.3g}")
+    assert e_all <= 1e-4 and e_mag <= 1e-4 and e_arg <= 1e-3
+    ctx.unload_scene(sid)
+
+
+def test_deterministic(ctx):
+    say("determinism")
+    s, tg, fg = scenes.config2()
+    sid = ctx.load_scene(s)
+    a = ctx.cfr(sid, tg, fg, 1).clone()
+    b = ctx.cfr(sid, tg, fg, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(a.view(torch.float32), b.view(torch.float32))
+    ctx.unload_scene(sid)
+
+
+def test_load_errors(ctx):
+    say("loader errors")
+    from paper_2205_00237_amd._abi import DrtError, DRT_E_INVAL, DRT_E_DEGENERATE, DRT_E_INCONSISTENT
+    s, tg, fg = scenes.config1()
+    bad = dict(s)
+    bad["ray_prim"] = s["ray_prim"].copy()
+    bad["ray_prim"][3, 0] = 999
+    with pytest.raises(DrtError) as e:
+        ctx.load_scene(bad)
+    assert e.value.status == DRT_E_INVAL
+    # Tx on the ground plane: the ground reflection is degenerate at t0
+    deg = dict(s)
+    deg["tx_p"] = np.array([0.0, 0.0, 0.0])
+    deg["rx_p"] = np.array([50.0, 0.0, 0.0])
+    with pytest.raises(DrtError) as e:
+        ctx.load_scene(deg)
+    assert e.value.status == DRT_E_DEGENERATE
+    q0 = np.zeros((25, 4, 3))
+    with pytest.raises(DrtError) as e:
+        ctx.load_scene(s, ray_q0=q0 + np.array([0, 0, 5.0]))
+    assert e.value.status == DRT_E_INCONSISTENT
+    # the oracle's t0 points are accepted
+    ref = oracle.extrapolate(s, np.array([0.0]), fg.f_c, keep_points=True)
+    for r in range(25):
+        for i, p in enumerate(ref["points"][r]):
+            q0[r, i] = p[0]
+    sid = ctx.load_scene(s, ray_q0=q0)
+    ctx.unload_scene(sid)

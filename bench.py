@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Throughput of the DRT hot path on one MI355X.
+
+A step is one drt_cfr call over the urban vehicular workload (5000 rays up to three
+reflections plus one diffraction among 20 moving boxes and 200 facades, 1000 instants of
+0.5 ms, 1024 subcarriers over 400 MHz at 28 GHz): body poses, per-(ray, instant)
+extrapolation and field coefficients, and the ray sum H(t, f), in split precision.  The
+metric is ray x time x frequency samples of H per second, with inputs resident in device
+memory.  Beside it: the binary64 GPU path on the same workload, the kernel-level roofline
+of the dominant kernel (timed with HIP events on its own stream), the CPU oracle on a
+bounded sample, and the serving mix (4096 Poisson requests over 64 resident scenes) with
+p50 / p99 latency.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR = 157.3e12      # MI355X published dense vector fp32 [flop/s]
+PEAK_FP64_VECTOR = 78.6e12
+FLOP_PER_SAMPLE = 8              # one complex rotation (6) + one complex accumulate (2)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(scene, tg, fg, budget_s=15.0):
+    """The oracle (numpy, one thread) on whole time rows of the same workload."""
+    import numpy as np
+    import oracle
+    R, K = len(scene["ray_nint"]), fg.n_sub
+    t = time.perf_counter()
+    oracle.run(scene, tg, fg, t_index=np.array([0]))
+    one = time.perf_counter() - t
+    rows = max(1, min(tg.n_steps, int(budget_s / max(one, 1e-3))))
+    idx = np.linspace(0, tg.n_steps - 1, rows).astype(int)
+    t = time.perf_counter()
+    oracle.run(scene, tg, fg, t_index=idx)
+    el = time.perf_counter() - t
+    return {"value": R * rows * K / el, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{rows} of {tg.n_steps} instants, all {R} rays and {K} subcarriers "
+                      f"({el:.1f} s, numpy float64, single thread)"}
+
+
+def serving(ctx, torch, n_requests):
+    """Config-5 mix: Poisson arrivals at 2000/s over 64 resident 20000-ray scenes."""
+    import numpy as np
+    from paper_2205_00237_amd import scenes
+    from paper_2205_00237_amd._abi import drt_now
+    from paper_2205_00237_amd.drt import DRT_SPLIT
+    t = time.perf_counter()
+    sids = [ctx.load_scene(s) for s in scenes.config5_scenes()]
+    load_s = time.perf_counter() - t
+    reqs = scenes.config5_requests(n_requests)
+    pending, lat, samples, t_last = {}, [], 0, 0.0
+    t_start = drt_now() + 0.05
+    i = 0
+    while i < len(reqs) or pending:
+        now = drt_now()
+        while i < len(reqs) and t_start + reqs[i].arrival <= now:
+            q = reqs[i]
+            H = torch.empty((q.n_steps, q.n_sub), dtype=torch.complex64, device="cuda")
+            tk = ctx.submit(sids[q.scene], q.n_rays, scenes.TimeGrid(q.dt, q.n_steps),
+                            scenes.FreqGrid(q.f_c, q.bandwidth, q.n_sub), H, DRT_SPLIT)
+            pending[tk] = (q, H)
+            i += 1
+        for tk in list(pending):
+            st = ctx.poll(tk)
+            if st[0] == 2 or st[0] < 0:
+                q, _ = pending.pop(tk)
+                if st[0] < 0:
+                    raise RuntimeError(f"request failed with status {st[0]}")
+                lat.append(st[3] - (t_start + q.arrival))
+                samples += q.n_rays * q.n_steps * q.n_sub
+                t_last = max(t_last, st[3])
+        if i < len(reqs) and not pending:
+            time.sleep(max(0.0, min(1e-4, t_start + reqs[i].arrival - drt_now())))
+    for s in sids:
+        ctx.unload_scene(s)
+    lat = np.array(lat)
+    span = t_last - (t_start + reqs[0].arrival)
+    return {"workload": f"{len(reqs)} requests, Poisson 2000/s, 64 resident scenes of 20000 rays, "
+                        "rays log-uniform 50-20000, 10-1000 instants of 1 ms, 64-2048 subcarriers, "
+                        "28/60 GHz, 400 MHz, split precision",
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "max_ms": float(lat.max() * 1e3), "samples_per_s": samples / span,
+            "offered_samples_per_s": samples / (reqs[-1].arrival - reqs[0].arrival),
+            "scene_load_s": load_s}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=4096)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: this build runs the hot path on a single MI355X and "
+              f"has no multi-GPU path (asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2205_00237_amd import scenes
+    from paper_2205_00237_amd.drt import Context, DRT_FP64, DRT_SPLIT
+
+    scene, tg, fg = scenes.config2()
+    R, T, K = len(scene["ray_nint"]), tg.n_steps, fg.n_sub
+    samples = R * T * K
+    ctx = Context(0)
+    t = time.perf_counter()
+    sid = ctx.load_scene(scene)
+    load_s = time.perf_counter() - t
+
+    H = torch.empty((T, K), dtype=torch.complex64, device="cuda")
+    step = lambda: ctx.cfr(sid, tg, fg, DRT_SPLIT, out=H)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    sec = timed_steps(step, args.steps, 0, torch)
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    log(f"split: {sec * 1e3:.3f} ms/step, kernels {prof}")
+
+    H64 = torch.empty((T, K), dtype=torch.complex128, device="cuda")
+    step64 = lambda: ctx.cfr(sid, tg, fg, DRT_FP64, out=H64)
+    ctx.profile(True)
+    sec64 = timed_steps(step64, max(3, args.steps // 2), 1, torch)
+    prof64 = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    log(f"fp64: {sec64 * 1e3:.3f} ms/step, kernels {prof64}")
+
+    # dominant kernel of the split step, against its roofline
+    name = max(prof, key=lambda k: prof[k][0])
+    ms_avg = prof[name][0] / max(1, prof[name][1])
+    if name == "cfr":
+        achieved = FLOP_PER_SAMPLE * samples / (ms_avg * 1e-3)
+        roof = {"kernel": "k_cfr (split)", "bound": "alu", "achieved": achieved / 1e12,
+                "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
+                "traffic": None, "avg_ms": ms_avg,
+                "per_unit": f"{FLOP_PER_SAMPLE} flop per (ray, instant, subcarrier) sample, {samples} samples per launch"}
+    else:
+        roof = {"kernel": name, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "avg_ms": ms_avg}
+    kernels = {k: {"avg_ms": v[0] / max(1, v[1]), "launches": v[1]} for k, v in prof.items() if v[1]}
+
+    out = {
+        "metric": "ray*time*freq samples/s of H(t,f), split-precision vs FP64 GPU; p99 latency",
+        "value": samples / sec, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "urban vehicular (configs[1]): 5000 rays <= 3R+1D, 20 moving boxes, "
+                               "200 facades, 1000 instants x 0.5 ms, 1024 subcarriers / 400 MHz at 28 GHz, "
+                               "split precision (f64 phase reduction, f32 phasor arithmetic)",
+                   "rays": R, "instants": T, "subcarriers": K, "parallelism": "single GPU"},
+        "fp64_gpu": {"value": samples / sec64, "ms_per_step": sec64 * 1e3, "dtype": "f64",
+                     "split_speedup": sec64 / sec},
+        "roofline": roof,
+        "kernels": kernels,
+        "scene_load_s": load_s,
+    }
+    ctx.unload_scene(sid)
+    if not args.no_serving:
+        log("serving mix ...")
+        out["serving"] = serving(ctx, torch, args.serving_requests)
+        out["p99_latency_ms"] = out["serving"]["p99_ms"]
+        out["p50_latency_ms"] = out["serving"]["p50_ms"]
+        log(f"serving: {out['serving']}")
+    ctx.close()
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(scene, tg, fg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -176,6 +176,18 @@ int drt_poll(drt_ctx *ctx, uint64_t ticket, drt_req_stat *stat);
 /* Seconds on the clock used by drt_req_stat. */
 double drt_now(void);
 
+/* Kernel timing (tracing aid).  While enabled, drt_extrapolate and drt_cfr record a
+ * hipEvent pair around each kernel they launch, on the caller's stream, so the figures are
+ * device durations of those kernels alone.  drt_profile_read waits for the recorded events
+ * and returns the totals since the last reset; index with enum drt_kernel_id. */
+enum drt_kernel_id { DRT_K_POSE = 0, DRT_K_GEOM = 1, DRT_K_CFR = 2, DRT_K_REDUCE = 3, DRT_K_COUNT = 4 };
+typedef struct {
+  double ms[DRT_K_COUNT];          /* summed device milliseconds per kernel */
+  int64_t launches[DRT_K_COUNT];   /* number of launches timed */
+} drt_profile;
+int drt_profile_enable(drt_ctx *ctx, int on);
+int drt_profile_read(drt_ctx *ctx, drt_profile *out, int reset);
+
 const char *drt_strerror(int status);
 const char *drt_last_error(void);
 

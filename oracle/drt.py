@@ -81,6 +81,7 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
     pols = scene["ray_pol"][rays, :n]
     slots = [_moved(scene, kinds[i], prims[:, i], poses, axis) for i in range(n)]
     valid = np.ones((Ng, T), dtype=bool)
+    degen = np.zeros((Ng, T), dtype=bool)   # a chain no instant can solve (diagnostic)
     extra = {}
 
     if n == 0:
@@ -99,14 +100,19 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
             B = mirror(B, p, nn)
         ed = slots[d]
         QD, zA, zB, rA, rB = edge_point(A, B, ed["a"], ed["e"])
-        pb, _, v1 = reflection_chain(TXg, QD, before)
-        pa, _, v2 = reflection_chain(QD, RXg, after)
+        pb, _, v1, d1 = reflection_chain(TXg, QD, before, return_den=True)
+        pa, _, v2, d2 = reflection_chain(QD, RXg, after, return_den=True)
         pts = pb + [QD] + pa
         valid &= v1 & v2 & (rA > RHO_MIN) & (rB > RHO_MIN)
+        degen = ~((rA > RHO_MIN) & (rB > RHO_MIN))
+        for den in d1 + d2:
+            degen |= den == 0
         extra = {"d": d, "A": A, "B": B, "QD": QD}
     else:
-        pts, _, v = reflection_chain(TXg, RXg, [(s["p"], s["n"]) for s in slots])
+        pts, _, v, dens = reflection_chain(TXg, RXg, [(s["p"], s["n"]) for s in slots], return_den=True)
         valid &= v
+        for den in dens:
+            degen |= den == 0
 
     verts = [TXg] + pts + [RXg]
     segs = [verts[i] - verts[i - 1] for i in range(1, n + 2)]
@@ -114,6 +120,8 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
     with np.errstate(divide="ignore", invalid="ignore"):
         khat = [s / l[..., None] for s, l in zip(segs, lens)]
     L = np.sum(lens, axis=0)
+    for ln in lens:
+        degen |= ~(ln > 0)
 
     # Doppler from the material velocities of the interaction points
     u = [np.broadcast_to(VTX[None], (Ng, T, 3))]
@@ -180,6 +188,7 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
         if key == "valid":
             continue
         out[key] = np.where(valid, out[key], 0)
+    out["degenerate"] = degen
     out["_pts"] = pts
     out["_khat"] = khat
     return out
@@ -201,6 +210,7 @@ def extrapolate(scene, dt, f_c, rays=None, chunk=256, keep_points=False):
     out = {k: np.zeros((R, T)) for k in ("L", "dop", "aod_az", "aod_el", "aoa_az", "aoa_el")}
     out["gain"] = np.zeros((R, T), dtype=np.complex128)
     out["valid"] = np.zeros((R, T), dtype=bool)
+    out["degenerate"] = np.zeros((R, T), dtype=bool)
     if keep_points:
         out["points"] = [None] * R
         out["khat"] = [None] * R

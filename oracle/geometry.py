@@ -31,11 +31,13 @@ def mirror(X, p, n):
     return X - 2.0 * dot(X - p, n)[..., None] * n
 
 
-def reflection_chain(src, dst, planes):
+def reflection_chain(src, dst, planes, return_den=False):
     """Reflection points from `src` to `dst` over the walls `planes` = [(p, n), ...].
 
     Returns (points [Q_1..Q_m], images [A_1..A_m], valid) where valid is the boolean
-    0 < s_m < 1 for every wall (all arrays broadcast over the leading dims)."""
+    0 < s_m < 1 for every wall (all arrays broadcast over the leading dims); with
+    return_den=True also the denominators (Q_{m+1}-A_m).n_m (zero: image line parallel
+    to the wall, a degenerate chain)."""
     images = []
     A = src
     for p, n in planes:
@@ -44,10 +46,12 @@ def reflection_chain(src, dst, planes):
     points = [None] * len(planes)
     valid = np.ones(np.broadcast_shapes(src.shape, dst.shape)[:-1], dtype=bool)
     nxt = dst
+    dens = [None] * len(planes)
     for m in range(len(planes) - 1, -1, -1):
         p, n = planes[m]
         num = dot(nxt - p, n)
         den = dot(nxt - images[m], n)
+        dens[m] = den
         with np.errstate(divide="ignore", invalid="ignore"):
             s = num / den
         ok = np.isfinite(s) & (s > 0.0) & (s < 1.0)
@@ -56,6 +60,8 @@ def reflection_chain(src, dst, planes):
         Q = nxt + s[..., None] * (images[m] - nxt)
         points[m] = Q
         nxt = Q
+    if return_den:
+        return points, images, valid, dens
     return points, images, valid
 
 

@@ -25,7 +25,9 @@ DRT_E_INCONSISTENT = -8
 DRT_FP64, DRT_SPLIT, DRT_NAIVE32 = 0, 1, 2
 
 EXPORTS = ("drt_create", "drt_destroy", "drt_load_scene", "drt_unload_scene", "drt_extrapolate",
-           "drt_cfr", "drt_submit", "drt_poll", "drt_now", "drt_strerror", "drt_last_error")
+           "drt_cfr", "drt_submit", "drt_poll", "drt_now", "drt_strerror", "drt_last_error",
+           "drt_profile_enable", "drt_profile_read")
+KERNELS = ("pose", "geom", "cfr", "reduce")
 
 _dp = C.POINTER(C.c_double)
 _u8p = C.POINTER(C.c_uint8)
@@ -79,6 +81,10 @@ class ReqStat(C.Structure):
                 ("t_done", C.c_double)]
 
 
+class Profile(C.Structure):
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
+
+
 class DrtError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -106,6 +112,8 @@ def _load():
         "drt_now": (C.c_double, []),
         "drt_strerror": (C.c_char_p, [C.c_int]),
         "drt_last_error": (C.c_char_p, []),
+        "drt_profile_enable": (C.c_int, [vp, C.c_int]),
+        "drt_profile_read": (C.c_int, [vp, C.POINTER(Profile), C.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -231,3 +239,14 @@ def drt_poll(ctx, ticket):
 
 def drt_now():
     return LIB.drt_now()
+
+
+def drt_profile_enable(ctx, on):
+    _check(LIB.drt_profile_enable(ctx, int(bool(on))), "drt_profile_enable")
+
+
+def drt_profile_read(ctx, reset=True):
+    """{kernel name: (total ms, launches)} since the last reset."""
+    p = Profile()
+    _check(LIB.drt_profile_read(ctx, C.byref(p), int(bool(reset))), "drt_profile_read")
+    return {k: (p.ms[i], p.launches[i]) for i, k in enumerate(KERNELS)}

@@ -104,6 +104,12 @@ struct drt_ctx {
   std::mutex scratch_mu;
   int target_waves = 16384;
 
+  // kernel timing
+  struct ProfRec { int kernel; hipEvent_t a, b; };
+  std::atomic<bool> prof{false};
+  std::mutex prof_mu;
+  std::vector<ProfRec> prof_recs;
+
   // serving
   std::vector<Slot_> slots;
   std::deque<Request*> queue;
@@ -375,6 +381,22 @@ static SceneView device_view(const Scene& s) {
   return v;
 }
 
+// Launch `fn` on stream st, bracketed by a hipEvent pair when kernel timing is on.
+template <class Fn>
+static hipError_t timed(drt_ctx* c, int kernel, hipStream_t st, Fn&& fn) {
+  if (!c || !c->prof.load()) return fn();
+  drt_ctx::ProfRec r{kernel, nullptr, nullptr};
+  hipError_t e;
+  if ((e = hipEventCreate(&r.a)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&r.b)) != hipSuccess) return e;
+  if ((e = hipEventRecord(r.a, st)) != hipSuccess) return e;
+  if ((e = fn()) != hipSuccess) return e;
+  if ((e = hipEventRecord(r.b, st)) != hipSuccess) return e;
+  std::lock_guard<std::mutex> g(c->prof_mu);
+  c->prof_recs.push_back(r);
+  return hipSuccess;
+}
+
 struct CfrPlan {
   CfrArgs a;
   size_t pose_off, rec_off, part_off, total;
@@ -395,19 +417,25 @@ static CfrPlan plan(drt_ctx* c, const Scene& s, int n_rays, int T, const drt_fre
   return p;
 }
 
-static int run_cfr(const Scene& s, int n_rays, const drt_time_grid* tg, const drt_freq_grid* fg, int prec,
-                   void* H, const CfrPlan& p, void* scratch, hipStream_t st) {
+static int run_cfr(drt_ctx* c, const Scene& s, int n_rays, const drt_time_grid* tg, const drt_freq_grid* fg,
+                   int prec, void* H, const CfrPlan& p, void* scratch, hipStream_t st) {
   char* base = (char*)scratch;
   int T = tg->n_steps;
-  HIP_OK(launch_pose((const DBody*)s.d_bodies.p, s.view.n_bodies, T, tg->dt, prec, base + p.pose_off, st));
+  HIP_OK(timed(c, DRT_K_POSE, st, [&] {
+    return launch_pose((const DBody*)s.d_bodies.p, s.view.n_bodies, T, tg->dt, prec, base + p.pose_off, st);
+  }));
   ExtrapOut none{};
-  HIP_OK(launch_geom(device_view(s), base + p.pose_off, T, tg->dt, fg->f_c, n_rays, prec, GEOM_ANCHOR, none,
-                     base + p.rec_off, p.a.df / 299792458.0, st));
+  HIP_OK(timed(c, DRT_K_GEOM, st, [&] {
+    return launch_geom(device_view(s), base + p.pose_off, T, tg->dt, fg->f_c, n_rays, prec, GEOM_ANCHOR, none,
+                       base + p.rec_off, p.a.df / 299792458.0, st);
+  }));
   if (p.a.G > 1) {
-    HIP_OK(launch_cfr(base + p.rec_off, p.a, prec, base + p.part_off, st));
-    HIP_OK(launch_reduce(base + p.part_off, p.a.G, size_t(T) * fg->n_sub, prec, H, st));
+    HIP_OK(timed(c, DRT_K_CFR, st, [&] { return launch_cfr(base + p.rec_off, p.a, prec, base + p.part_off, st); }));
+    HIP_OK(timed(c, DRT_K_REDUCE, st, [&] {
+      return launch_reduce(base + p.part_off, p.a.G, size_t(T) * fg->n_sub, prec, H, st);
+    }));
   } else {
-    HIP_OK(launch_cfr(base + p.rec_off, p.a, prec, H, st));
+    HIP_OK(timed(c, DRT_K_CFR, st, [&] { return launch_cfr(base + p.rec_off, p.a, prec, H, st); }));
   }
   return DRT_OK;
 }
@@ -488,7 +516,7 @@ static void serve_loop(drt_ctx* c) {
       int st = ensure_scratch(c, free_slot->scratch, q->footprint, free_slot->stream);
       if (st == DRT_OK) {
         CfrPlan p = plan(c, *q->scene, q->r.n_rays, q->r.tg.n_steps, &q->r.fg, q->r.precision);
-        st = run_cfr(*q->scene, q->r.n_rays, &q->r.tg, &q->r.fg, q->r.precision, q->r.H, p,
+        st = run_cfr(nullptr, *q->scene, q->r.n_rays, &q->r.tg, &q->r.fg, q->r.precision, q->r.H, p,
                      free_slot->scratch.buf.p, free_slot->stream);
       }
       if (st == DRT_OK && hipEventRecord(free_slot->done, free_slot->stream) != hipSuccess) st = DRT_E_DEVICE;
@@ -639,9 +667,13 @@ int drt_extrapolate(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_g
   std::lock_guard<std::mutex> g(c->scratch_mu);
   Scratch& sc = c->scratch[hs];
   if ((st = ensure_scratch(c, sc, pose_bytes(s->view.n_bodies, T, prec), hs))) return st;
-  HIP_OK(launch_pose((const DBody*)s->d_bodies.p, s->view.n_bodies, T, tg->dt, prec, sc.buf.p, hs));
+  HIP_OK(timed(c, DRT_K_POSE, hs, [&] {
+    return launch_pose((const DBody*)s->d_bodies.p, s->view.n_bodies, T, tg->dt, prec, sc.buf.p, hs);
+  }));
   ExtrapOut eo{out->L, out->dop, out->aod_az, out->aod_el, out->aoa_az, out->aoa_el, out->gain, out->valid};
-  HIP_OK(launch_geom(device_view(*s), sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_EXTRAP, eo, nullptr, 0.0, hs));
+  HIP_OK(timed(c, DRT_K_GEOM, hs, [&] {
+    return launch_geom(device_view(*s), sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_EXTRAP, eo, nullptr, 0.0, hs);
+  }));
   return DRT_OK;
 }
 
@@ -665,7 +697,34 @@ int drt_cfr(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg,
   std::lock_guard<std::mutex> g(c->scratch_mu);
   Scratch& sc = c->scratch[hs];
   if ((st = ensure_scratch(c, sc, p.total, hs))) return st;
-  return run_cfr(*s, n_rays, tg, fg, prec, H, p, sc.buf.p, hs);
+  return run_cfr(c, *s, n_rays, tg, fg, prec, H, p, sc.buf.p, hs);
+}
+
+int drt_profile_enable(drt_ctx* c, int on) {
+  if (!c) return fail(DRT_E_INVAL, "null context");
+  c->prof.store(on != 0);
+  return DRT_OK;
+}
+
+int drt_profile_read(drt_ctx* c, drt_profile* out, int reset) {
+  if (!c || !out) return fail(DRT_E_INVAL, "null argument");
+  std::lock_guard<std::mutex> g(c->prof_mu);
+  std::memset(out, 0, sizeof *out);
+  for (auto& r : c->prof_recs) {
+    HIP_OK(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+    out->ms[r.kernel] += ms;
+    out->launches[r.kernel] += 1;
+  }
+  if (reset) {
+    for (auto& r : c->prof_recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    c->prof_recs.clear();
+  }
+  return DRT_OK;
 }
 
 int drt_submit(drt_ctx* c, const drt_request* r, uint64_t* ticket) {

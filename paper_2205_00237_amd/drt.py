@@ -81,3 +81,9 @@ class Context:
 
     def poll(self, ticket):
         return _abi.drt_poll(self.ctx, ticket)
+
+    def profile(self, on=True):
+        _abi.drt_profile_enable(self.ctx, on)
+
+    def profile_read(self, reset=True):
+        return _abi.drt_profile_read(self.ctx, reset)

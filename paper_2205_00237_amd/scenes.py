@@ -311,19 +311,49 @@ def config2(seed=2, scale=1, separation=None, bearing=None, n_facades=200, n_box
             box_planes.append((pl, _pol_for_normal(bx["face_geom"][name][1])))
         box_edges.extend(bx["edges"])
 
-    def pick_plane(prev):
+    def coplanar(p, q):
+        # two walls on one plane in succession: the second image undoes the first
+        n1, n2 = b.planes[p][3], b.planes[q][3]
+        return abs(abs(np.dot(n1, n2)) - 1.0) < 1e-12 and abs(np.dot(b.planes[q][2] - b.planes[p][2], n1)) < 1e-9
+
+    def horizontal(p):
+        return abs(b.planes[p][3][2]) > 0.5
+
+    def pick_plane(prev, n_horizontal):
+        # at most one horizontal box face per ray: all roofs (floors) share one height and
+        # both terminals are 1.5 m high, so two horizontal mirrors cancel in z and leave the
+        # last image line parallel to its wall at every instant
         while True:
             if rng.random() < 0.8:
                 pl, pol = facade_planes[rng.integers(len(facade_planes))], POL_PERP
             else:
                 pl, pol = box_planes[rng.integers(len(box_planes))]
-            if pl != prev:
+            if n_horizontal and horizontal(pl):
+                continue
+            if prev < 0 or not coplanar(prev, pl):
                 return pl, pol
 
     def pick_edge():
         if rng.random() < 0.7:
             return facade_edges[rng.integers(len(facade_edges))]
         return box_edges[rng.integers(len(box_edges))]
+
+    def edge_in_plane(e, p):
+        # a reflection on a wall that contains the ray's diffracting edge makes two
+        # interaction points coincide
+        _, a0, e0, _, _, _ = b.edges[e]
+        p0, n0 = b.planes[p][2], b.planes[p][3]
+        return abs(np.dot(e0, n0)) < 1e-12 and abs(np.dot(a0 - p0, n0)) < 1e-9
+
+    def compatible(kinds, prims):
+        # no wall of the ray may contain the ray's diffracting edge
+        for i, (ki, pi) in enumerate(zip(kinds, prims)):
+            if ki != KIND_D:
+                continue
+            for kj, pj in zip(kinds, prims):
+                if kj == KIND_R and edge_in_plane(pi, pj):
+                    return False
+        return True
 
     for sig, count in CONFIG2_MIX:
         for _ in range(count * scale):
@@ -338,19 +368,23 @@ def config2(seed=2, scale=1, separation=None, bearing=None, n_facades=200, n_box
                 slots.insert(int(rng.integers(4)), "D")
             else:
                 slots = list(sig)
-            kinds, prims, pols, prev = [], [], [], -1
-            for k in slots:
-                if k == "R":
-                    pl, pol = pick_plane(prev)
-                    kinds.append(KIND_R)
-                    prims.append(pl)
-                    pols.append(pol)
-                    prev = pl
-                else:
-                    kinds.append(KIND_D)
-                    prims.append(pick_edge())
-                    pols.append(POL_PERP)
-                    prev = -1
+            while True:
+                kinds, prims, pols, prev, nh = [], [], [], -1, 0
+                for k in slots:
+                    if k == "R":
+                        pl, pol = pick_plane(prev, nh)
+                        nh += horizontal(pl)
+                        kinds.append(KIND_R)
+                        prims.append(pl)
+                        pols.append(pol)
+                        prev = pl
+                    else:
+                        kinds.append(KIND_D)
+                        prims.append(pick_edge())
+                        pols.append(POL_PERP)
+                        prev = -1
+                if compatible(kinds, prims):
+                    break
             b.add_ray(kinds, prims, pols)
     scene = b.build(tx_p=tx_p, tx_v=tx_v, tx_a=tx_a, rx_p=rx_p, rx_v=rx_v, rx_a=rx_a)
     return scene, TimeGrid(dt, n_steps), FreqGrid(f_c, bandwidth, n_sub)

@@ -78,7 +78,7 @@ def test_admission_and_errors(ctx):
     small = Context(0, hbm_cap_bytes=64 << 20)
     try:
         sid = small.load_scene(s)
-        big_tg = scenes.TimeGrid(1e-3, 100000)
+        big_tg = scenes.TimeGrid(1e-3, 2_000_000)   # ~1.2 GB of per-(ray, instant) records
         H = torch.empty((1, 1), dtype=torch.complex64, device="cuda")
         with pytest.raises(DrtError) as e:
             small.submit(sid, 25, big_tg, scenes.FreqGrid(28e9, 1e8, 4096), H)

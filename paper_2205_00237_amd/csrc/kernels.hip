@@ -39,13 +39,14 @@ __global__ __launch_bounds__(256) void k_pose(const DBody* bodies, int nb, int T
 // ---------------------------------------------------------------------------------------
 
 struct RecS { double L; float gr, gi, zr, zi; };       // split: 24 B
+struct RecM { float ar, ai, phi0, phiB, phi1, pad; };   // split, MFMA path: 24 B (phases in cycles)
 struct RecD { double L, gr, gi, zr, zi; };              // binary64: 40 B
 struct RecN { float L, gr, gi, zr, zi, pad; };          // naive binary32: 24 B
 
 template <class F, int MODE, int PREC>
 __global__ __launch_bounds__(256) void k_geom(SceneView sc, const typename Vec2<F>::type* pose, int T,
                                               double dt, double f_c, int n_rays, int nchunk,
-                                              ExtrapOut eo, void* rec, double df_over_c) {
+                                              ExtrapOut eo, void* rec, AnchorParams ap) {
   int wave = __builtin_amdgcn_readfirstlane(int(blockIdx.x) * 4 + int(threadIdx.x >> 6));
   int lane = threadIdx.x & 63;
   int r = wave / nchunk, chunk = wave - (wave / nchunk) * nchunk;
@@ -92,9 +93,21 @@ __global__ __launch_bounds__(256) void k_geom(SceneView sc, const typename Vec2<
         reinterpret_cast<float2*>(eo.gain)[o] = {float(res.gain.re), float(res.gain.im)};
     }
     if (eo.valid) eo.valid[o] = res.ok ? 1 : 0;
+  } else if constexpr (MODE == GEOM_ANCHOR_MFMA) {
+    // phases of the first subcarrier, of one row block and of one subcarrier, each reduced
+    // modulo one cycle in binary64 before rounding to binary32
+    size_t o = (size_t(chunk) * n_rays + r) * 64 + lane;
+    if (!active) res.gain = cx<F>(F(0), F(0));
+    double L = double(res.L);
+    double p0 = L * ap.f0c, pB = L * ap.fBc, p1 = L * ap.f1c;
+    p0 -= floor(p0);
+    pB -= floor(pB);
+    p1 -= floor(p1);
+    reinterpret_cast<RecM*>(rec)[o] = {float(res.gain.re), float(res.gain.im), float(p0), float(pB), float(p1), 0.f};
   } else {
     size_t o = (size_t(chunk) * n_rays + r) * 64 + lane;
     if (!active) res.gain = cx<F>(F(0), F(0));
+    const double df_over_c = ap.f1c;
     if constexpr (PREC == DRT_FP64) {
       double cz = double(res.L) * df_over_c;
       cz -= floor(cz);
@@ -222,6 +235,99 @@ __global__ __launch_bounds__(256) void k_cfr(const void* rec, CfrArgs a, void* o
   }
 }
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Split-precision ray sum as complex GEMMs on the matrix cores.  With k = k1 B + k2,
+// exp(-j 2 pi f_k L/c) = exp(-j 2 pi (f_0 + k1 B df) L/c) exp(-j 2 pi k2 df L/c), so for one
+// instant H[k1 B + k2] = sum_r U[k1][r] V[r][k2] with U = a exp(-j 2 pi (f_0 + k1 B df) L/c)
+// and V = exp(-j 2 pi k2 df L/c): each U is reused B times and each V K/B times.  The
+// complex product is the real GEMM [U_re U_im] [[V_re V_im], [-V_im V_re]]; one
+// v_mfma_f32_16x16x4_f32 takes two rays (4 contraction slots: ray0 re, ray0 im, ray1 re,
+// ray1 im).  Lane l supplies A[row l%16][slot l/16] and B[slot l/16][column l%16] and owns
+// accumulator rows 4(l/16)..4(l/16)+3 of column l%16.  Rows are k1 (MT tiles of 16), columns
+// are [C_re for k2 < B | C_im for k2 < B] (NT tiles of 16, B = 8 NT).  Operands are
+// generated on the vector ALU from the record's binary64-reduced phases: the U row phase
+// phi0 + k1 phiB and the V column phase k2 phi1 (cycles, k1, k2 < 64) are formed in binary32
+// and fed to v_sin/v_cos, which take revolutions.
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void k_cfr_mfma(const RecM* rec, CfrArgs a, float* out) {
+  constexpr int B = 8 * NT;
+  __shared__ floatx4 red[3][64][MT * NT];
+  int bid = xcd_remap(blockIdx.x, gridDim.x);
+  if (bid >= a.n_blocks) return;
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int g = bid % a.G, t = bid / a.G;
+  int slice = g * 4 + wv;
+  int r0 = slice * a.slice_len;
+  int r1 = min(a.n_rays, r0 + a.slice_len);
+  const int m = lane & 15, kslot = lane >> 4, rsel = kslot >> 1, part = kslot & 1;
+  const size_t base = size_t(t >> 6) * a.n_rays * 64 + (t & 63);
+  floatx4 acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int r = r0; r < r1; r += 2) {
+    int rr = r + rsel;
+    RecM q{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (rr < r1) q = rec[base + size_t(rr) * 64];
+    float av[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      float ph = __builtin_amdgcn_fractf(__builtin_fmaf(float(mt * 16 + m), q.phiB, q.phi0));
+      float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
+      av[mt] = part == 0 ? q.ar * c + q.ai * s : q.ai * c - q.ar * s;   // Re / Im of a e^{-j 2 pi ph}
+    }
+    float bv[NT];
+    if constexpr (NT == 1) {
+      float ph = __builtin_amdgcn_fractf(float(m & 7) * q.phi1);
+      float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
+      bv[0] = (m >> 3) == 0 ? (part == 0 ? c : s) : (part == 0 ? -s : c);
+    } else {
+#pragma unroll
+      for (int h = 0; h < NT / 2; ++h) {
+        float ph = __builtin_amdgcn_fractf(float(h * 16 + m) * q.phi1);
+        float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
+        bv[h] = part == 0 ? c : s;                 // C_re columns: V_re, -V_im
+        bv[h + NT / 2] = part == 0 ? -s : c;       // C_im columns: V_im, V_re
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
+  }
+  if (wv > 0) {
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) red[wv - 1][lane][i * NT + j] = acc[i][j];
+  }
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[i][j] += red[w][lane][i * NT + j];
+  float* dst = out + (a.G > 1 ? size_t(g) * a.T * a.K * 2 : 0) + size_t(t) * a.K * 2;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int k1 = mt * 16 + 4 * kslot + v;
+        int col = nt * 16 + m;
+        int k2 = col % B, isim = col / B;
+        int k = k1 * B + k2;
+        if (k1 < a.K1 && k < a.K) dst[size_t(k) * 2 + isim] = acc[mt][nt][v];
+      }
+}
+
 template <class C>
 __global__ __launch_bounds__(256) void k_reduce(const C* part, int G, size_t n, C* H) {
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -272,38 +378,64 @@ size_t record_bytes(int n_rays, int T, int prec) {
 
 template <int MODE>
 static hipError_t launch_geom_mode(const SceneView& sc, const void* pose, int T, double dt, double f_c,
-                                   int n_rays, int prec, const ExtrapOut& eo, void* rec, double df_over_c,
+                                   int n_rays, int prec, const ExtrapOut& eo, void* rec, const AnchorParams& ap,
                                    hipStream_t st) {
   int nchunk = (T + 63) / 64;
   long waves = long(n_rays) * nchunk;
   dim3 grid((waves + 3) / 4);
-  if (prec == DRT_FP64)
-    hipLaunchKernelGGL((k_geom<double, MODE, DRT_FP64>), grid, dim3(256), 0, st, sc, (const double2*)pose, T,
-                       dt, f_c, n_rays, nchunk, eo, rec, df_over_c);
-  else if (prec == DRT_SPLIT)
+  if constexpr (MODE == GEOM_ANCHOR_MFMA) {
     hipLaunchKernelGGL((k_geom<double, MODE, DRT_SPLIT>), grid, dim3(256), 0, st, sc, (const double2*)pose, T,
-                       dt, f_c, n_rays, nchunk, eo, rec, df_over_c);
-  else
-    hipLaunchKernelGGL((k_geom<float, MODE, DRT_NAIVE32>), grid, dim3(256), 0, st, sc, (const float2*)pose, T,
-                       dt, f_c, n_rays, nchunk, eo, rec, df_over_c);
+                       dt, f_c, n_rays, nchunk, eo, rec, ap);
+  } else {
+    if (prec == DRT_FP64)
+      hipLaunchKernelGGL((k_geom<double, MODE, DRT_FP64>), grid, dim3(256), 0, st, sc, (const double2*)pose, T,
+                         dt, f_c, n_rays, nchunk, eo, rec, ap);
+    else if (prec == DRT_SPLIT)
+      hipLaunchKernelGGL((k_geom<double, MODE, DRT_SPLIT>), grid, dim3(256), 0, st, sc, (const double2*)pose, T,
+                         dt, f_c, n_rays, nchunk, eo, rec, ap);
+    else
+      hipLaunchKernelGGL((k_geom<float, MODE, DRT_NAIVE32>), grid, dim3(256), 0, st, sc, (const float2*)pose, T,
+                         dt, f_c, n_rays, nchunk, eo, rec, ap);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_geom(const SceneView& sc, const void* pose, int T, double dt, double f_c, int n_rays, int prec,
-                       int mode, const ExtrapOut& eo, void* rec, double df_over_c, hipStream_t st) {
+                       int mode, const ExtrapOut& eo, void* rec, const AnchorParams& ap, hipStream_t st) {
   if (n_rays == 0 || T == 0) return hipSuccess;
   if (mode == GEOM_EXTRAP)
-    return launch_geom_mode<GEOM_EXTRAP>(sc, pose, T, dt, f_c, n_rays, prec, eo, rec, df_over_c, st);
-  return launch_geom_mode<GEOM_ANCHOR>(sc, pose, T, dt, f_c, n_rays, prec, eo, rec, df_over_c, st);
+    return launch_geom_mode<GEOM_EXTRAP>(sc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
+  if (mode == GEOM_ANCHOR_MFMA)
+    return launch_geom_mode<GEOM_ANCHOR_MFMA>(sc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
+  return launch_geom_mode<GEOM_ANCHOR>(sc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
 }
 
-CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_waves) {
+CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_waves, int prec) {
   CfrArgs a{};
   a.n_rays = n_rays;
   a.T = T;
   a.K = K;
   a.f0 = f0;
   a.df = df;
+  a.path = CFR_VALU;
+  if (prec == DRT_SPLIT && K <= 2048) {
+    a.path = CFR_MFMA;
+    a.NT = K <= 64 ? 1 : (K <= 256 ? 2 : 4);
+    a.B = 8 * a.NT;
+    a.K1 = (K + a.B - 1) / a.B;
+    a.MT = (a.K1 + 15) / 16;
+    if (a.MT == 3) a.MT = 4;
+    long tiles = T;
+    int G = int((target_waves + 4 * tiles - 1) / (4 * tiles));
+    int maxG = (n_rays + 4 * kMinSlice - 1) / (4 * kMinSlice);
+    if (G > maxG) G = maxG;
+    if (G < 1) G = 1;
+    a.G = G;
+    a.slice_len = (n_rays + 4 * G - 1) / (4 * G);
+    a.slice_len += a.slice_len & 1;     // rays go through the matrix cores in pairs
+    a.n_blocks = int(tiles * G);
+    return a;
+  }
   int blocks_k = (K + kNK - 1) / kNK;   // subcarrier blocks of kNK
   int kb = 1;
   while (kb < blocks_k && kb < 64) kb <<= 1;
@@ -324,6 +456,23 @@ CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_wave
 
 hipError_t launch_cfr(const void* rec, const CfrArgs& a, int prec, void* out, hipStream_t st) {
   int grid = ((a.n_blocks + 7) / 8) * 8;
+  if (a.path == CFR_MFMA) {
+    const RecM* r = (const RecM*)rec;
+    float* o = (float*)out;
+    if (a.MT == 1 && a.NT == 1)
+      hipLaunchKernelGGL((k_cfr_mfma<1, 1>), dim3(grid), dim3(256), 0, st, r, a, o);
+    else if (a.MT == 1 && a.NT == 2)
+      hipLaunchKernelGGL((k_cfr_mfma<1, 2>), dim3(grid), dim3(256), 0, st, r, a, o);
+    else if (a.MT == 1 && a.NT == 4)
+      hipLaunchKernelGGL((k_cfr_mfma<1, 4>), dim3(grid), dim3(256), 0, st, r, a, o);
+    else if (a.MT == 2 && a.NT == 4)
+      hipLaunchKernelGGL((k_cfr_mfma<2, 4>), dim3(grid), dim3(256), 0, st, r, a, o);
+    else if (a.MT == 4 && a.NT == 4)
+      hipLaunchKernelGGL((k_cfr_mfma<4, 4>), dim3(grid), dim3(256), 0, st, r, a, o);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (prec == DRT_FP64)
     hipLaunchKernelGGL((k_cfr<DRT_FP64, kNK>), dim3(grid), dim3(256), 0, st, rec, a, out);
   else if (prec == DRT_SPLIT)

@@ -407,7 +407,7 @@ static CfrPlan plan(drt_ctx* c, const Scene& s, int n_rays, int T, const drt_fre
   int K = fg->n_sub;
   double df = fg->bandwidth / K;
   double f0 = fg->f_c - double(K / 2) * df;
-  p.a = plan_cfr(n_rays, T, K, f0, df, c->target_waves);
+  p.a = plan_cfr(n_rays, T, K, f0, df, c->target_waves, prec);
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   size_t cbytes = prec == DRT_FP64 ? 16 : 8;
   p.pose_off = 0;
@@ -425,9 +425,12 @@ static int run_cfr(drt_ctx* c, const Scene& s, int n_rays, const drt_time_grid* 
     return launch_pose((const DBody*)s.d_bodies.p, s.view.n_bodies, T, tg->dt, prec, base + p.pose_off, st);
   }));
   ExtrapOut none{};
+  const double inv_c = 1.0 / 299792458.0;
+  AnchorParams ap{p.a.f0 * inv_c, double(p.a.B) * p.a.df * inv_c, p.a.df * inv_c};
+  int mode = p.a.path == CFR_MFMA ? GEOM_ANCHOR_MFMA : GEOM_ANCHOR;
   HIP_OK(timed(c, DRT_K_GEOM, st, [&] {
-    return launch_geom(device_view(s), base + p.pose_off, T, tg->dt, fg->f_c, n_rays, prec, GEOM_ANCHOR, none,
-                       base + p.rec_off, p.a.df / 299792458.0, st);
+    return launch_geom(device_view(s), base + p.pose_off, T, tg->dt, fg->f_c, n_rays, prec, mode, none,
+                       base + p.rec_off, ap, st);
   }));
   if (p.a.G > 1) {
     HIP_OK(timed(c, DRT_K_CFR, st, [&] { return launch_cfr(base + p.rec_off, p.a, prec, base + p.part_off, st); }));
@@ -672,7 +675,8 @@ int drt_extrapolate(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_g
   }));
   ExtrapOut eo{out->L, out->dop, out->aod_az, out->aod_el, out->aoa_az, out->aoa_el, out->gain, out->valid};
   HIP_OK(timed(c, DRT_K_GEOM, hs, [&] {
-    return launch_geom(device_view(*s), sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_EXTRAP, eo, nullptr, 0.0, hs);
+    return launch_geom(device_view(*s), sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_EXTRAP, eo, nullptr,
+                       AnchorParams{0.0, 0.0, 0.0}, hs);
   }));
   return DRT_OK;
 }

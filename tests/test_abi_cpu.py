@@ -8,11 +8,16 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "drt.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
 
 
-def _declared():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|double|const char \*)\s*(drt_\w+)\s*\(", text, re.M)))
+def _declared(headers=(HEADER,)):
+    names = set()
+    for h in headers:
+        text = open(h).read()
+        names |= set(re.findall(r"^\s*(?:int|double|const char \*)\s*(drt_\w+)\s*\(", text, re.M))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -25,9 +30,12 @@ def test_header_declares_the_boundary():
 def test_library_exports_every_declared_symbol():
     from paper_2205_00237_amd import _abi
     lib = ctypes.CDLL(_abi.LIB_PATH)
-    for n in _declared():
+    every = _declared(HEADERS)
+    assert len(every) > len(_declared())
+    for n in every:
         assert hasattr(lib, n), n
     assert set(_abi.EXPORTS) == set(_declared())
+    assert set(_abi.EXPORTS) | set(_abi.PROBE_EXPORTS) == set(every)
 
 
 def test_host_only_helpers():

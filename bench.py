@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=4096)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (reference dispatch for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -145,13 +148,21 @@ def main():
     ctx.profile(False)
     log(f"split: {sec * 1e3:.3f} ms/step, kernels {prof}")
 
-    H64 = torch.empty((T, K), dtype=torch.complex128, device="cuda")
-    step64 = lambda: ctx.cfr(sid, tg, fg, DRT_FP64, out=H64)
-    ctx.profile(True)
-    sec64 = timed_steps(step64, max(3, args.steps // 2), 1, torch)
-    prof64 = ctx.profile_read(reset=True)
-    ctx.profile(False)
-    log(f"fp64: {sec64 * 1e3:.3f} ms/step, kernels {prof64}")
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    sec64 = None
+    if not args.no_fp64:
+        H64 = torch.empty((T, K), dtype=torch.complex128, device="cuda")
+        step64 = lambda: ctx.cfr(sid, tg, fg, DRT_FP64, out=H64)
+        ctx.profile(True)
+        sec64 = timed_steps(step64, max(3, args.steps // 2), 1, torch)
+        prof64 = ctx.profile_read(reset=True)
+        ctx.profile(False)
+        log(f"fp64: {sec64 * 1e3:.3f} ms/step, kernels {prof64}")
 
     # dominant kernel of the split step, against its roofline
     name = max(prof, key=lambda k: prof[k][0])
@@ -176,8 +187,8 @@ def main():
                                "200 facades, 1000 instants x 0.5 ms, 1024 subcarriers / 400 MHz at 28 GHz, "
                                "split precision (f64 phase reduction, f32 phasor arithmetic)",
                    "rays": R, "instants": T, "subcarriers": K, "parallelism": "single GPU"},
-        "fp64_gpu": {"value": samples / sec64, "ms_per_step": sec64 * 1e3, "dtype": "f64",
-                     "split_speedup": sec64 / sec},
+        "fp64_gpu": ({"value": samples / sec64, "ms_per_step": sec64 * 1e3, "dtype": "f64",
+                      "split_speedup": sec64 / sec} if sec64 else None),
         "roofline": roof,
         "kernels": kernels,
         "scene_load_s": load_s,

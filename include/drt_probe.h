@@ -22,6 +22,13 @@ extern "C" {
  * layout. */
 int drt_probe_mfma_f32_16x16x4(const float *A, const float *B, float *D);
 
+/* One wave executes v_mfma_f32_16x16x32_f16 with lane l supplying the 8 half-precision
+ * values A[l%16][8*(l/16)+j] (A 16x32 row-major, 512 IEEE binary16 values as uint16) and
+ * B[8*(l/16)+j][l%16] (B 32x16 row-major), j = 0..7 in vector order, accumulator zero, and
+ * writes D[4*(l/16)+v][l%16] (16x16 row-major floats).  D equals A.B when that is the
+ * hardware's lane layout. */
+int drt_probe_mfma_f16_16x16x32(const uint16_t *A, const uint16_t *B, float *D);
+
 /* s[i] = v_sin_f32(x[i]), c[i] = v_cos_f32(x[i]): the hardware sine and cosine of an
  * angle given in revolutions (sin(2 pi x)).  n >= 0 elements. */
 int drt_probe_sincos_rev(const float *x, int32_t n, float *s, float *c);

@@ -27,7 +27,7 @@ DRT_FP64, DRT_SPLIT, DRT_NAIVE32 = 0, 1, 2
 EXPORTS = ("drt_create", "drt_destroy", "drt_load_scene", "drt_unload_scene", "drt_extrapolate",
            "drt_cfr", "drt_submit", "drt_poll", "drt_now", "drt_strerror", "drt_last_error",
            "drt_profile_enable", "drt_profile_read")
-PROBE_EXPORTS = ("drt_probe_mfma_f32_16x16x4", "drt_probe_sincos_rev")
+PROBE_EXPORTS = ("drt_probe_mfma_f32_16x16x4", "drt_probe_mfma_f16_16x16x32", "drt_probe_sincos_rev")
 KERNELS = ("pose", "geom", "cfr", "reduce")
 
 _dp = C.POINTER(C.c_double)
@@ -117,6 +117,7 @@ def _load():
         "drt_profile_read": (C.c_int, [vp, C.POINTER(Profile), C.c_int]),
         "drt_probe_mfma_f32_16x16x4": (C.c_int, [vp, vp, vp]),
         "drt_probe_sincos_rev": (C.c_int, [vp, C.c_int32, vp, vp]),
+        "drt_probe_mfma_f16_16x16x32": (C.c_int, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -263,3 +264,8 @@ def drt_probe_mfma_f32_16x16x4(A_ptr, B_ptr, D_ptr):
 def drt_probe_sincos_rev(x_ptr, n, s_ptr, c_ptr):
     _check(LIB.drt_probe_sincos_rev(C.c_void_p(int(x_ptr)), int(n), C.c_void_p(int(s_ptr)),
                                     C.c_void_p(int(c_ptr))), "drt_probe_sincos_rev")
+
+
+def drt_probe_mfma_f16_16x16x32(A_ptr, B_ptr, D_ptr):
+    _check(LIB.drt_probe_mfma_f16_16x16x32(C.c_void_p(int(A_ptr)), C.c_void_p(int(B_ptr)),
+                                           C.c_void_p(int(D_ptr))), "drt_probe_mfma_f16_16x16x32")

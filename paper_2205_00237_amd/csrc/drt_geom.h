@@ -218,9 +218,21 @@ DRT_HD Cx<F> fresnel(F cos_t, const DMat& m, F lam, int pol) {
 // tail is (sqrt(pi)/2) e^{-j pi/4} erfc(e^{j pi/4} sqrt X) and the even continued fraction
 // of erfc gives F(X) = jX / t with t = z2 + 1/2 - (1*2/4)/(z2 + 5/2 - (3*4/4)/(z2 + 9/2 ...)),
 // z2 = jX, evaluated backwards from a fixed depth.
+// Series below xs; above it the continued-fraction depth that reaches the type's precision
+// shrinks quickly with X (binary64: 28 levels at X = 6, 3 beyond X = 1000).
 template <class F> struct FxParams;
-template <> struct FxParams<double> { static constexpr double xs = 4.5; static constexpr int ns = 36, depth = 32; };
-template <> struct FxParams<float> { static constexpr float xs = 4.0f; static constexpr int ns = 22, depth = 14; };
+template <> struct FxParams<double> {
+  static constexpr double xs = 6.0;
+  static constexpr int ns = 40;
+  static DRT_HD int depth(double X) {
+    return X < 8 ? 28 : X < 12 ? 20 : X < 20 ? 14 : X < 40 ? 9 : X < 100 ? 6 : X < 1000 ? 4 : 3;
+  }
+};
+template <> struct FxParams<float> {
+  static constexpr float xs = 4.0f;
+  static constexpr int ns = 22;
+  static DRT_HD int depth(float X) { return X < 12.f ? 8 : X < 40.f ? 4 : 2; }
+};
 
 template <class F> DRT_HD Cx<F> utd_transition(F X) {
   if (X <= F(0)) return cx<F>(F(0), F(0));
@@ -243,9 +255,9 @@ template <class F> DRT_HD Cx<F> utd_transition(F X) {
     Cx<F> e = cx<F>(mcos(X), msin(X));
     return (F(2) * x) * (cx<F>(F(0), F(1)) * (e * tail));
   }
-  Cx<F> t = cx<F>(F(4 * FxParams<F>::depth + 1) * F(0.5), X);
-#pragma unroll 4
-  for (int n = FxParams<F>::depth; n >= 1; --n) {
+  const int depth = FxParams<F>::depth(X);
+  Cx<F> t = cx<F>(F(4 * depth + 1) * F(0.5), X);
+  for (int n = depth; n >= 1; --n) {
     F c = F((2 * n - 1) * (2 * n)) * F(0.25);
     Cx<F> q = cdiv(cx<F>(c, F(0)), t);
     t = cx<F>(F(4 * n - 3) * F(0.5) - q.re, X - q.im);
@@ -465,6 +477,34 @@ DRT_HD int prim_body(const SceneView& sc, int kind, int prim) {
   if (kind == DRT_R) return sc.planes[prim].body;
   if (kind == DRT_D) return sc.edges[prim].body;
   return sc.tiles[prim].body;
+}
+
+// Dispatch on the signature code within one class.
+template <class F, int CLS, class Fn> DRT_HD auto with_signature_in(int code, Fn&& fn) {
+  if constexpr (CLS == CLS_R) {
+    switch (code) {
+      case SIG_LOS: return fn.template operator()<0, -1, false>();
+      case SIG_R1: return fn.template operator()<1, -1, false>();
+      case SIG_R2: return fn.template operator()<2, -1, false>();
+      case SIG_R3: return fn.template operator()<3, -1, false>();
+      default: return fn.template operator()<4, -1, false>();
+    }
+  } else if constexpr (CLS == CLS_D) {
+    switch (code) {
+      case SIG_D: return fn.template operator()<1, 0, false>();
+      case SIG_DR: return fn.template operator()<2, 0, false>();
+      case SIG_RD: return fn.template operator()<2, 1, false>();
+      case SIG_DRR: return fn.template operator()<3, 0, false>();
+      case SIG_RDR: return fn.template operator()<3, 1, false>();
+      case SIG_RRD: return fn.template operator()<3, 2, false>();
+      case SIG_DRRR: return fn.template operator()<4, 0, false>();
+      case SIG_RDRR: return fn.template operator()<4, 1, false>();
+      case SIG_RRDR: return fn.template operator()<4, 2, false>();
+      default: return fn.template operator()<4, 3, false>();
+    }
+  } else {
+    return fn.template operator()<1, -1, true>();
+  }
 }
 
 // Dispatch on the signature code (DRay::code) to the matching template instance.

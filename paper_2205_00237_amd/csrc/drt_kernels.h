@@ -10,7 +10,7 @@
 namespace drt {
 
 enum GeomMode { GEOM_EXTRAP = 0, GEOM_ANCHOR = 1, GEOM_ANCHOR_MFMA = 2 };
-enum CfrPath { CFR_VALU = 0, CFR_MFMA = 1 };
+enum CfrPath { CFR_VALU = 0, CFR_MFMA = 1, CFR_MFMA16 = 2 };
 
 constexpr int kNK = 16;          // subcarriers walked by one lane from its phase anchor
 constexpr int kMinSlice = 8;     // fewest rays per wave slice of the ray sum
@@ -40,13 +40,20 @@ struct AnchorParams {
   double f1c;   // df / c: phase step between adjacent subcarriers
 };
 
+// Rays of each signature class (indices into the scene's ray table, ascending) for one call.
+struct RayClasses {
+  const int32_t* order[CLS_COUNT];
+  int count[CLS_COUNT];
+};
+
 size_t pose_bytes(int nb, int T, int prec);
 size_t record_bytes(int n_rays, int T, int prec);
-CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_waves, int prec);
+CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_waves, int prec, int split_path);
 
 hipError_t launch_pose(const DBody* bodies, int nb, int T, double dt, int prec, void* out, hipStream_t st);
-hipError_t launch_geom(const SceneView& sc, const void* pose, int T, double dt, double f_c, int n_rays, int prec,
-                       int mode, const ExtrapOut& eo, void* rec, const AnchorParams& ap, hipStream_t st);
+hipError_t launch_geom(const SceneView& sc, const RayClasses& rc, const void* pose, int T, double dt, double f_c,
+                       int n_rays, int prec, int mode, const ExtrapOut& eo, void* rec, const AnchorParams& ap,
+                       hipStream_t st);
 hipError_t launch_cfr(const void* rec, const CfrArgs& a, int prec, void* out, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_reduce(const void* part, int G, size_t n, int prec, void* H, hipStream_t st);

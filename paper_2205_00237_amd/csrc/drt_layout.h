@@ -3,6 +3,7 @@
 // wave-uniform) and a 32-byte record per ray.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "../../include/drt.h"
@@ -40,6 +41,12 @@ enum SigCode : uint8_t {
   SIG_D, SIG_DR, SIG_RD, SIG_DRR, SIG_RDR, SIG_RRD, SIG_DRRR, SIG_RDRR, SIG_RRDR, SIG_RRRD,
   SIG_S, SIG_COUNT
 };
+
+// Signature classes launched as separate kernels so that each gets its own register budget.
+enum SigClass { CLS_R = 0, CLS_D = 1, CLS_S = 2, CLS_COUNT = 3 };
+inline __host__ __device__ int sig_class(int code) {
+  return code <= SIG_R4 ? CLS_R : (code == SIG_S ? CLS_S : CLS_D);
+}
 
 struct DRay {           // 48 B
   uint8_t nint, code, dpos, pad;

@@ -43,14 +43,15 @@ struct RecM { float ar, ai, phi0, phiB, phi1, pad; };   // split, MFMA path: 24 
 struct RecD { double L, gr, gi, zr, zi; };              // binary64: 40 B
 struct RecN { float L, gr, gi, zr, zi, pad; };          // naive binary32: 24 B
 
-template <class F, int MODE, int PREC>
-__global__ __launch_bounds__(256) void k_geom(SceneView sc, const typename Vec2<F>::type* pose, int T,
-                                              double dt, double f_c, int n_rays, int nchunk,
-                                              ExtrapOut eo, void* rec, AnchorParams ap) {
+template <class F, int MODE, int PREC, int CLS>
+__global__ __launch_bounds__(256) void k_geom(SceneView sc, const int32_t* order, int count,
+                                              const typename Vec2<F>::type* pose, int T, double dt, double f_c,
+                                              int n_rays, int nchunk, ExtrapOut eo, void* rec, AnchorParams ap) {
   int wave = __builtin_amdgcn_readfirstlane(int(blockIdx.x) * 4 + int(threadIdx.x >> 6));
   int lane = threadIdx.x & 63;
-  int r = wave / nchunk, chunk = wave - (wave / nchunk) * nchunk;
-  if (r >= n_rays) return;
+  int i = wave / nchunk, chunk = wave - (wave / nchunk) * nchunk;
+  if (i >= count) return;
+  int r = __builtin_amdgcn_readfirstlane(order[i]);
   int t = chunk * 64 + lane;
   bool active = t < T;
   int tq = active ? t : T - 1;
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(256) void k_geom(SceneView sc, const typename Vec2<
     }
   }
   F fc = F(f_c);
-  RayResult<F> res = with_signature<F>(ray.code, [&]<int N, int DP, bool SCAT>() {
+  RayResult<F> res = with_signature_in<F, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
     return eval_ray<F, N, DP, SCAT>(sc, ray, sl, TX, VTX, RX, VRX, fc);
   });
 
@@ -96,8 +97,8 @@ __global__ __launch_bounds__(256) void k_geom(SceneView sc, const typename Vec2<
   } else if constexpr (MODE == GEOM_ANCHOR_MFMA) {
     // phases of the first subcarrier, of one row block and of one subcarrier, each reduced
     // modulo one cycle in binary64 before rounding to binary32
-    size_t o = (size_t(chunk) * n_rays + r) * 64 + lane;
-    if (!active) res.gain = cx<F>(F(0), F(0));
+    if (!active) return;
+    size_t o = size_t(t) * n_rays + r;      // instant-major: a ray-sum wave streams its instant
     double L = double(res.L);
     double p0 = L * ap.f0c, pB = L * ap.fBc, p1 = L * ap.f1c;
     p0 -= floor(p0);
@@ -261,17 +262,32 @@ __global__ __launch_bounds__(256) void k_cfr_mfma(const RecM* rec, CfrArgs a, fl
   int r0 = slice * a.slice_len;
   int r1 = min(a.n_rays, r0 + a.slice_len);
   const int m = lane & 15, kslot = lane >> 4, rsel = kslot >> 1, part = kslot & 1;
-  const size_t base = size_t(t >> 6) * a.n_rays * 64 + (t & 63);
+  const RecM* rt = rec + size_t(t) * a.n_rays;
   floatx4 acc[MT][NT];
 #pragma unroll
   for (int i = 0; i < MT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (int r = r0; r < r1; r += 2) {
-    int rr = r + rsel;
-    RecM q{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (rr < r1) q = rec[base + size_t(rr) * 64];
+  // 64 rays' records per coalesced load (one per lane), the next batch in flight while the
+  // current one is consumed pair by pair through cross-lane shuffles
+  auto load = [&](int rb) {
+    int r = rb + lane;
+    return r < r1 ? rt[r] : RecM{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  };
+  RecM cur = load(r0);
+  for (int rb = r0; rb < r1; rb += 64) {
+    RecM nxt = load(rb + 64);
+    const int npairs = min(32, (r1 - rb + 1) >> 1);
+#pragma unroll 2
+    for (int p = 0; p < npairs; ++p) {
+    const int src = 2 * p + rsel;
+    RecM q;
+    q.ar = __shfl(cur.ar, src);
+    q.ai = __shfl(cur.ai, src);
+    q.phi0 = __shfl(cur.phi0, src);
+    q.phiB = __shfl(cur.phiB, src);
+    q.phi1 = __shfl(cur.phi1, src);
     float av[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
@@ -298,6 +314,8 @@ __global__ __launch_bounds__(256) void k_cfr_mfma(const RecM* rec, CfrArgs a, fl
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
         acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
+    }
+    cur = nxt;
   }
   if (wv > 0) {
 #pragma unroll
@@ -321,6 +339,167 @@ __global__ __launch_bounds__(256) void k_cfr_mfma(const RecM* rec, CfrArgs a, fl
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int k1 = mt * 16 + 4 * kslot + v;
+        int col = nt * 16 + m;
+        int k2 = col % B, isim = col / B;
+        int k = k1 * B + k2;
+        if (k1 < a.K1 && k < a.K) dst[size_t(k) * 2 + isim] = acc[mt][nt][v];
+      }
+}
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __fp16 fp16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// hi + lo binary16 pairs of two binary32 values, each pair packed in one 32-bit word: hi
+// rounds toward zero, lo = x - hi is representable to 2^-11 of itself, so hi + lo keeps
+// ~22 bits of x.
+__device__ __forceinline__ void split_pair(float x, float y, unsigned& hi, unsigned& lo) {
+  fp16x2 h = __builtin_amdgcn_cvt_pkrtz(x, y);
+  fp16x2 l = __builtin_amdgcn_cvt_pkrtz(x - float(h[0]), y - float(h[1]));
+  hi = __builtin_bit_cast(unsigned, h);
+  lo = __builtin_bit_cast(unsigned, l);
+}
+
+// (p, q) -> (-q, p) on a packed binary16 pair: swap the halves, flip the new low sign
+__device__ __forceinline__ unsigned rot_pair(unsigned w) { return ((w >> 16) | (w << 16)) ^ 0x8000u; }
+
+// Split-precision ray sum on the binary16 matrix cores.  Same factorisation as k_cfr_mfma
+// (H[k1 B + k2] = sum_r U[k1][r] V[r][k2]), but each binary32 operand x is carried as
+// hi + lo in binary16 and the product as hi.hi + hi.lo + lo.hi (three
+// v_mfma_f32_16x16x32_f16 per tile, relative error ~2^-22), accumulated in binary32.
+// One instruction contracts 32 slots = 16 rays x (re, im): lane l owns A[row l%16][slots
+// 8(l/16)..+7] and B[slots 8(l/16)..+7][column l%16], i.e. rays 4(l/16)..+3 of each block
+// of 16, and generates whole complex U and V values for them.  Each wave scales its ray
+// slice's gains by a power of two that puts the largest component near 2^13 (binary16
+// tops out at 65504 and is normal down to 2^-14) and divides it out of its accumulators
+// before the slices are summed.
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void k_cfr_mfma16(const RecM* rec, CfrArgs a, float* out) {
+  constexpr int B = 8 * NT;
+  __shared__ floatx4 red[3][64][MT * NT];
+  int bid = xcd_remap(blockIdx.x, gridDim.x);
+  if (bid >= a.n_blocks) return;
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int g = bid % a.G, t = bid / a.G;
+  int slice = g * 4 + wv;
+  int r0 = slice * a.slice_len;
+  int r1 = min(a.n_rays, r0 + a.slice_len);
+  const int m = lane & 15, grp = lane >> 4;
+  const RecM* rt = rec + size_t(t) * a.n_rays;
+  floatx4 acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  auto load = [&](int rb) {
+    int r = rb + lane;
+    return r < r1 ? rt[r] : RecM{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  };
+  float amax = 0.f;
+  for (int rb = r0; rb < r1; rb += 64) {
+    RecM q = load(rb);
+    amax = fmaxf(amax, fmaxf(fabsf(q.ar), fabsf(q.ai)));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+  int e2 = 0;
+  (void)frexpf(amax, &e2);                       // amax < 2^e2
+  const float kScale = amax > 0.f ? ldexpf(1.f, 13 - e2) : 1.f;
+  const float kInv = 1.f / kScale;
+  RecM cur = load(r0);
+  for (int rb = r0; rb < r1; rb += 64) {
+    RecM nxt = load(rb + 64);
+    const int nblk = min(4, (r1 - rb + 15) >> 4);
+    for (int bk = 0; bk < nblk; ++bk) {
+      u32x4 ahw[MT], alw[MT], bhw[NT], blw[NT];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int src = bk * 16 + grp * 4 + j;
+        const float ar = __shfl(cur.ar, src) * kScale, ai = __shfl(cur.ai, src) * kScale;
+        const float phi0 = __shfl(cur.phi0, src), phiB = __shfl(cur.phiB, src), phi1 = __shfl(cur.phi1, src);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          float ph = __builtin_amdgcn_fractf(__builtin_fmaf(float(mt * 16 + m), phiB, phi0));
+          float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
+          unsigned h, l;
+          split_pair(ar * c + ai * s, ai * c - ar * s, h, l);   // U = a e^{-j 2 pi ph}
+          ahw[mt][j] = h;
+          alw[mt][j] = l;
+        }
+        if constexpr (NT == 1) {
+          float ph = __builtin_amdgcn_fractf(float(m & 7) * phi1);
+          float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
+          unsigned h, l;
+          split_pair(c, s, h, l);                     // C_re column: (V_re, -V_im)
+          if ((m >> 3) != 0) {                        // C_im column: (V_im, V_re)
+            h = rot_pair(h);
+            l = rot_pair(l);
+          }
+          bhw[0][j] = h;
+          blw[0][j] = l;
+        } else {
+#pragma unroll
+          for (int hh = 0; hh < NT / 2; ++hh) {
+            float ph = __builtin_amdgcn_fractf(float(hh * 16 + m) * phi1);
+            float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
+            unsigned h, l;
+            split_pair(c, s, h, l);
+            bhw[hh][j] = h;
+            blw[hh][j] = l;
+            bhw[hh + NT / 2][j] = rot_pair(h);
+            blw[hh + NT / 2][j] = rot_pair(l);
+          }
+        }
+      }
+      half8 ah[MT], al[MT], bh[NT], bl[NT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        ah[mt] = __builtin_bit_cast(half8, ahw[mt]);
+        al[mt] = __builtin_bit_cast(half8, alw[mt]);
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        bh[nt] = __builtin_bit_cast(half8, bhw[nt]);
+        bl[nt] = __builtin_bit_cast(half8, blw[nt]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mt], bh[nt], acc[mt][nt], 0, 0, 0);
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mt], bl[nt], acc[mt][nt], 0, 0, 0);
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[mt], bh[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+    cur = nxt;
+  }
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] *= kInv;      // exact: a power of two
+  if (wv > 0) {
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) red[wv - 1][lane][i * NT + j] = acc[i][j];
+  }
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[i][j] += red[w][lane][i * NT + j];
+  float* dst = out + (a.G > 1 ? size_t(g) * a.T * a.K * 2 : 0) + size_t(t) * a.K * 2;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int k1 = mt * 16 + 4 * grp + v;
         int col = nt * 16 + m;
         int k2 = col % B, isim = col / B;
         int k = k1 * B + k2;
@@ -376,41 +555,57 @@ size_t record_bytes(int n_rays, int T, int prec) {
   return size_t((T + 63) / 64) * n_rays * 64 * per;
 }
 
-template <int MODE>
-static hipError_t launch_geom_mode(const SceneView& sc, const void* pose, int T, double dt, double f_c,
-                                   int n_rays, int prec, const ExtrapOut& eo, void* rec, const AnchorParams& ap,
-                                   hipStream_t st) {
+template <class F, int MODE, int PREC>
+static void launch_classes(const SceneView& sc, const RayClasses& rc, const void* pose, int T, double dt,
+                           double f_c, int n_rays, const ExtrapOut& eo, void* rec, const AnchorParams& ap,
+                           hipStream_t st) {
+  using P = const typename Vec2<F>::type*;
   int nchunk = (T + 63) / 64;
-  long waves = long(n_rays) * nchunk;
-  dim3 grid((waves + 3) / 4);
+  for (int c = 0; c < CLS_COUNT; ++c) {
+    if (rc.count[c] == 0) continue;
+    long waves = long(rc.count[c]) * nchunk;
+    dim3 grid((waves + 3) / 4);
+    if (c == CLS_R)
+      hipLaunchKernelGGL((k_geom<F, MODE, PREC, CLS_R>), grid, dim3(256), 0, st, sc, rc.order[c], rc.count[c],
+                         (P)pose, T, dt, f_c, n_rays, nchunk, eo, rec, ap);
+    else if (c == CLS_D)
+      hipLaunchKernelGGL((k_geom<F, MODE, PREC, CLS_D>), grid, dim3(256), 0, st, sc, rc.order[c], rc.count[c],
+                         (P)pose, T, dt, f_c, n_rays, nchunk, eo, rec, ap);
+    else
+      hipLaunchKernelGGL((k_geom<F, MODE, PREC, CLS_S>), grid, dim3(256), 0, st, sc, rc.order[c], rc.count[c],
+                         (P)pose, T, dt, f_c, n_rays, nchunk, eo, rec, ap);
+  }
+}
+
+template <int MODE>
+static hipError_t launch_geom_mode(const SceneView& sc, const RayClasses& rc, const void* pose, int T, double dt,
+                                   double f_c, int n_rays, int prec, const ExtrapOut& eo, void* rec,
+                                   const AnchorParams& ap, hipStream_t st) {
   if constexpr (MODE == GEOM_ANCHOR_MFMA) {
-    hipLaunchKernelGGL((k_geom<double, MODE, DRT_SPLIT>), grid, dim3(256), 0, st, sc, (const double2*)pose, T,
-                       dt, f_c, n_rays, nchunk, eo, rec, ap);
+    launch_classes<double, MODE, DRT_SPLIT>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
   } else {
     if (prec == DRT_FP64)
-      hipLaunchKernelGGL((k_geom<double, MODE, DRT_FP64>), grid, dim3(256), 0, st, sc, (const double2*)pose, T,
-                         dt, f_c, n_rays, nchunk, eo, rec, ap);
+      launch_classes<double, MODE, DRT_FP64>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
     else if (prec == DRT_SPLIT)
-      hipLaunchKernelGGL((k_geom<double, MODE, DRT_SPLIT>), grid, dim3(256), 0, st, sc, (const double2*)pose, T,
-                         dt, f_c, n_rays, nchunk, eo, rec, ap);
+      launch_classes<double, MODE, DRT_SPLIT>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
     else
-      hipLaunchKernelGGL((k_geom<float, MODE, DRT_NAIVE32>), grid, dim3(256), 0, st, sc, (const float2*)pose, T,
-                         dt, f_c, n_rays, nchunk, eo, rec, ap);
+      launch_classes<float, MODE, DRT_NAIVE32>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_geom(const SceneView& sc, const void* pose, int T, double dt, double f_c, int n_rays, int prec,
-                       int mode, const ExtrapOut& eo, void* rec, const AnchorParams& ap, hipStream_t st) {
+hipError_t launch_geom(const SceneView& sc, const RayClasses& rc, const void* pose, int T, double dt, double f_c,
+                       int n_rays, int prec, int mode, const ExtrapOut& eo, void* rec, const AnchorParams& ap,
+                       hipStream_t st) {
   if (n_rays == 0 || T == 0) return hipSuccess;
   if (mode == GEOM_EXTRAP)
-    return launch_geom_mode<GEOM_EXTRAP>(sc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
+    return launch_geom_mode<GEOM_EXTRAP>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
   if (mode == GEOM_ANCHOR_MFMA)
-    return launch_geom_mode<GEOM_ANCHOR_MFMA>(sc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
-  return launch_geom_mode<GEOM_ANCHOR>(sc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
+    return launch_geom_mode<GEOM_ANCHOR_MFMA>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
+  return launch_geom_mode<GEOM_ANCHOR>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
 }
 
-CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_waves, int prec) {
+CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_waves, int prec, int split_path) {
   CfrArgs a{};
   a.n_rays = n_rays;
   a.T = T;
@@ -418,8 +613,8 @@ CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_wave
   a.f0 = f0;
   a.df = df;
   a.path = CFR_VALU;
-  if (prec == DRT_SPLIT && K <= 2048) {
-    a.path = CFR_MFMA;
+  if (prec == DRT_SPLIT && K <= 2048 && split_path != CFR_VALU) {
+    a.path = split_path;
     a.NT = K <= 64 ? 1 : (K <= 256 ? 2 : 4);
     a.B = 8 * a.NT;
     a.K1 = (K + a.B - 1) / a.B;
@@ -432,7 +627,8 @@ CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_wave
     if (G < 1) G = 1;
     a.G = G;
     a.slice_len = (n_rays + 4 * G - 1) / (4 * G);
-    a.slice_len += a.slice_len & 1;     // rays go through the matrix cores in pairs
+    const int gran = a.path == CFR_MFMA16 ? 16 : 2;   // rays per matrix instruction
+    a.slice_len = (a.slice_len + gran - 1) / gran * gran;
     a.n_blocks = int(tiles * G);
     return a;
   }
@@ -456,22 +652,24 @@ CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_wave
 
 hipError_t launch_cfr(const void* rec, const CfrArgs& a, int prec, void* out, hipStream_t st) {
   int grid = ((a.n_blocks + 7) / 8) * 8;
-  if (a.path == CFR_MFMA) {
+  if (a.path == CFR_MFMA || a.path == CFR_MFMA16) {
     const RecM* r = (const RecM*)rec;
     float* o = (float*)out;
-    if (a.MT == 1 && a.NT == 1)
-      hipLaunchKernelGGL((k_cfr_mfma<1, 1>), dim3(grid), dim3(256), 0, st, r, a, o);
-    else if (a.MT == 1 && a.NT == 2)
-      hipLaunchKernelGGL((k_cfr_mfma<1, 2>), dim3(grid), dim3(256), 0, st, r, a, o);
-    else if (a.MT == 1 && a.NT == 4)
-      hipLaunchKernelGGL((k_cfr_mfma<1, 4>), dim3(grid), dim3(256), 0, st, r, a, o);
-    else if (a.MT == 2 && a.NT == 4)
-      hipLaunchKernelGGL((k_cfr_mfma<2, 4>), dim3(grid), dim3(256), 0, st, r, a, o);
-    else if (a.MT == 4 && a.NT == 4)
-      hipLaunchKernelGGL((k_cfr_mfma<4, 4>), dim3(grid), dim3(256), 0, st, r, a, o);
-    else
-      return hipErrorInvalidValue;
-    return hipGetLastError();
+#define DRT_LAUNCH_MFMA(MT_, NT_)                                                                   \
+  if (a.MT == MT_ && a.NT == NT_) {                                                               \
+    if (a.path == CFR_MFMA16)                                                                     \
+      hipLaunchKernelGGL((k_cfr_mfma16<MT_, NT_>), dim3(grid), dim3(256), 0, st, r, a, o);        \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_cfr_mfma<MT_, NT_>), dim3(grid), dim3(256), 0, st, r, a, o);          \
+    return hipGetLastError();                                                                     \
+  }
+    DRT_LAUNCH_MFMA(1, 1)
+    DRT_LAUNCH_MFMA(1, 2)
+    DRT_LAUNCH_MFMA(1, 4)
+    DRT_LAUNCH_MFMA(2, 4)
+    DRT_LAUNCH_MFMA(4, 4)
+#undef DRT_LAUNCH_MFMA
+    return hipErrorInvalidValue;
   }
   if (prec == DRT_FP64)
     hipLaunchKernelGGL((k_cfr<DRT_FP64, kNK>), dim3(grid), dim3(256), 0, st, rec, a, out);

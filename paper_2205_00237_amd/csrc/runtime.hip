@@ -2,11 +2,13 @@
 // and the serving loop (continuous batching of channel-prediction requests).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -65,7 +67,8 @@ struct Scene {
   std::vector<DEdge> edges;
   std::vector<DTile> tiles;
   std::vector<DRay> rays;
-  DevBuf d_bodies, d_mats, d_planes, d_edges, d_tiles, d_rays;
+  std::vector<int32_t> cls_rays[CLS_COUNT];   // ray indices of each signature class, ascending
+  DevBuf d_bodies, d_mats, d_planes, d_edges, d_tiles, d_rays, d_order;
   size_t bytes = 0;
   int inflight = 0;
 };
@@ -103,6 +106,7 @@ struct drt_ctx {
   std::map<hipStream_t, Scratch> scratch;   // per caller stream (drt_extrapolate / drt_cfr)
   std::mutex scratch_mu;
   int target_waves = 16384;
+  int split_path = CFR_MFMA16;               // ray-sum kernel of DRT_SPLIT (DRT_CFR_KERNEL)
 
   // kernel timing
   struct ProfRec { int kernel; hipEvent_t a, b; };
@@ -297,6 +301,7 @@ static int validate_and_pack(const drt_scene_desc* d, Scene& s) {
     int dpos;
     R.code = uint8_t(sig_code(n, R.kind, &dpos));
     R.dpos = uint8_t(dpos);
+    s.cls_rays[sig_class(R.code)].push_back(r);
   }
 
   // host view for the t0 checks
@@ -357,6 +362,20 @@ static void free_scene(drt_ctx* c, Scene& s) {
   dev_free(c, s.d_edges);
   dev_free(c, s.d_tiles);
   dev_free(c, s.d_rays);
+  dev_free(c, s.d_order);
+}
+
+// The rays [0, n_rays) of each signature class for one call.
+static RayClasses classes(const Scene& s, int n_rays) {
+  RayClasses rc{};
+  size_t off = 0;
+  for (int c = 0; c < CLS_COUNT; ++c) {
+    const auto& v = s.cls_rays[c];
+    rc.order[c] = (const int32_t*)s.d_order.p + off;
+    rc.count[c] = int(std::lower_bound(v.begin(), v.end(), n_rays) - v.begin());
+    off += v.size();
+  }
+  return rc;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -407,7 +426,7 @@ static CfrPlan plan(drt_ctx* c, const Scene& s, int n_rays, int T, const drt_fre
   int K = fg->n_sub;
   double df = fg->bandwidth / K;
   double f0 = fg->f_c - double(K / 2) * df;
-  p.a = plan_cfr(n_rays, T, K, f0, df, c->target_waves, prec);
+  p.a = plan_cfr(n_rays, T, K, f0, df, c->target_waves, prec, c->split_path);
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   size_t cbytes = prec == DRT_FP64 ? 16 : 8;
   p.pose_off = 0;
@@ -427,10 +446,10 @@ static int run_cfr(drt_ctx* c, const Scene& s, int n_rays, const drt_time_grid* 
   ExtrapOut none{};
   const double inv_c = 1.0 / 299792458.0;
   AnchorParams ap{p.a.f0 * inv_c, double(p.a.B) * p.a.df * inv_c, p.a.df * inv_c};
-  int mode = p.a.path == CFR_MFMA ? GEOM_ANCHOR_MFMA : GEOM_ANCHOR;
+  int mode = p.a.path == CFR_VALU ? GEOM_ANCHOR : GEOM_ANCHOR_MFMA;
   HIP_OK(timed(c, DRT_K_GEOM, st, [&] {
-    return launch_geom(device_view(s), base + p.pose_off, T, tg->dt, fg->f_c, n_rays, prec, mode, none,
-                       base + p.rec_off, ap, st);
+    return launch_geom(device_view(s), classes(s, n_rays), base + p.pose_off, T, tg->dt, fg->f_c, n_rays, prec,
+                       mode, none, base + p.rec_off, ap, st);
   }));
   if (p.a.G > 1) {
     HIP_OK(timed(c, DRT_K_CFR, st, [&] { return launch_cfr(base + p.rec_off, p.a, prec, base + p.part_off, st); }));
@@ -577,6 +596,13 @@ int drt_create(int device, uint64_t hbm_cap_bytes, drt_ctx** out) {
   auto c = std::make_unique<drt_ctx>();
   c->device = device;
   c->cap = hbm_cap_bytes ? hbm_cap_bytes : uint64_t(0.9 * double(total_b));
+  // tuning / comparison knob: which ray-sum kernel DRT_SPLIT uses
+  if (const char* k = std::getenv("DRT_CFR_KERNEL")) {
+    if (!std::strcmp(k, "valu")) c->split_path = CFR_VALU;
+    else if (!std::strcmp(k, "mfma32")) c->split_path = CFR_MFMA;
+    else if (!std::strcmp(k, "mfma16")) c->split_path = CFR_MFMA16;
+    else return fail(DRT_E_INVAL, "DRT_CFR_KERNEL=%s: expected valu, mfma32 or mfma16", k);
+  }
   *out = c.release();
   return DRT_OK;
 }
@@ -621,6 +647,12 @@ int drt_load_scene(drt_ctx* c, const drt_scene_desc* d, uint32_t* id) {
     free_scene(c, *s);
     return st;
   }
+  std::vector<int32_t> order;
+  for (int k = 0; k < CLS_COUNT; ++k) order.insert(order.end(), s->cls_rays[k].begin(), s->cls_rays[k].end());
+  if ((st = upload(c, s->d_order, order.data(), order.size()))) {
+    free_scene(c, *s);
+    return st;
+  }
   s->view.mats = nullptr;
   s->view.planes = nullptr;
   s->view.edges = nullptr;
@@ -628,7 +660,7 @@ int drt_load_scene(drt_ctx* c, const drt_scene_desc* d, uint32_t* id) {
   s->view.bodies = nullptr;
   s->view.rays = nullptr;
   s->bytes = s->d_bodies.bytes + s->d_mats.bytes + s->d_planes.bytes + s->d_edges.bytes + s->d_tiles.bytes +
-             s->d_rays.bytes;
+             s->d_rays.bytes + s->d_order.bytes;
   std::lock_guard<std::mutex> g(c->mu);
   s->id = c->next_scene++;
   *id = s->id;
@@ -675,8 +707,8 @@ int drt_extrapolate(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_g
   }));
   ExtrapOut eo{out->L, out->dop, out->aod_az, out->aod_el, out->aoa_az, out->aoa_el, out->gain, out->valid};
   HIP_OK(timed(c, DRT_K_GEOM, hs, [&] {
-    return launch_geom(device_view(*s), sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_EXTRAP, eo, nullptr,
-                       AnchorParams{0.0, 0.0, 0.0}, hs);
+    return launch_geom(device_view(*s), classes(*s, n_rays), sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_EXTRAP,
+                       eo, nullptr, AnchorParams{0.0, 0.0, 0.0}, hs);
   }));
   return DRT_OK;
 }

@@ -209,3 +209,33 @@ def test_load_errors(ctx):
             q0[r, i] = p[0]
     sid = ctx.load_scene(s, ray_q0=q0)
     ctx.unload_scene(sid)
+
+
+@pytest.mark.parametrize("kernel", ["valu", "mfma32", "mfma16"])
+def test_split_ray_sum_kernels(kernel, monkeypatch):
+    """Every split-precision ray-sum kernel (direct VALU recurrence, complex GEMM on fp32
+    matrix instructions, complex GEMM on split binary16 matrix instructions) meets the split
+    tolerance on the urban workload's sampled instants and on ragged subcarrier counts."""
+    say(f"split ray-sum kernel {kernel}")
+    from paper_2205_00237_amd.drt import Context
+    monkeypatch.setenv("DRT_CFR_KERNEL", kernel)
+    c = Context(0)
+    try:
+        s, tg, fg = scenes.config2()
+        sid = c.load_scene(s)
+        rows = np.array([0, 77, 640, 999])
+        _, Href = oracle.run(s, tg, fg, t_index=rows)
+        H = c.cfr(sid, tg, fg, 1).cpu().numpy().astype(np.complex128)[rows]
+        e_all, e_mag, e_arg = h_errors(H, Href)
+        say(f"  {kernel}: H errors all {e_all:.3g} mag {e_mag:.3g} arg {e_arg:.3g}")
+        assert e_all <= 1e-4 and e_mag <= 1e-4 and e_arg <= 1e-3
+        for K in (17, 64, 200, 256, 500, 2048):
+            fgk = scenes.FreqGrid(60e9, 400e6, K)
+            tgk = scenes.TimeGrid(1e-3, 70)
+            _, Hk = oracle.run(s, tgk, fgk, rays=np.arange(700), t_index=np.array([0, 33, 69]))
+            Gk = c.cfr(sid, tgk, fgk, 1, n_rays=700).cpu().numpy().astype(np.complex128)[[0, 33, 69]]
+            e_all, e_mag, e_arg = h_errors(Gk, Hk)
+            assert e_all <= 1e-4 and e_mag <= 1e-4 and e_arg <= 1e-3, (K, e_all, e_mag, e_arg)
+        c.unload_scene(sid)
+    finally:
+        c.close()

@@ -22,6 +22,21 @@ def test_mfma_16x16x4_lane_layout():
     assert np.array_equal(dD.cpu().numpy(), A @ B)
 
 
+def test_mfma_f16_16x16x32_lane_layout():
+    print("probe: mfma 16x16x32 f16 layout", flush=True)
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_00237_amd import _abi
+    rng = np.random.default_rng(2)
+    A = rng.integers(-8, 8, (16, 32)).astype(np.float16)
+    B = rng.integers(-8, 8, (32, 16)).astype(np.float16)
+    dA = torch.from_numpy(A.view(np.uint16).astype(np.int16)).cuda()
+    dB = torch.from_numpy(B.view(np.uint16).astype(np.int16)).cuda()
+    dD = torch.zeros((16, 16), dtype=torch.float32, device="cuda")
+    _abi.drt_probe_mfma_f16_16x16x32(dA.data_ptr(), dB.data_ptr(), dD.data_ptr())
+    assert np.array_equal(dD.cpu().numpy(), A.astype(np.float32) @ B.astype(np.float32))
+
+
 def test_hardware_sincos_on_revolutions():
     print("probe: v_sin/v_cos accuracy", flush=True)
     if not torch.cuda.is_available():

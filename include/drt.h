@@ -49,9 +49,10 @@ enum drt_status {
 };
 
 /* Arithmetic of a call.  DRT_FP64: everything in binary64, gains and H complex128.
- * DRT_SPLIT: geometry and gains in binary64, the per-sample phasor work of H in binary32
- * after reducing the carrier phase f*L/c modulo one cycle in binary64; gains complex64
- * and H complex64.  DRT_NAIVE32: geometry, gains, phase and H all in binary32 (for the
+ * DRT_SPLIT: geometry (interaction points, path length, Doppler, carrier-phase reduction
+ * f*L/c modulo one cycle, shadow-boundary distances of the wedge terms) in binary64; field
+ * coefficients and angles in binary32 from those binary64 quantities; the per-sample phasor
+ * work of H in binary32 / split binary16 on the matrix cores; gains complex64 and H complex64.  DRT_NAIVE32: geometry, gains, phase and H all in binary32 (for the
  * precision sweep only). */
 enum drt_precision { DRT_FP64 = 0, DRT_SPLIT = 1, DRT_NAIVE32 = 2 };
 

@@ -154,8 +154,7 @@ DRT_HD void reflect_chain(V3<F> src, V3<F> dst, const Slot<F>* w, V3<F>* Q, bool
 }
 
 constexpr double kRhoMin = 1e-9;    // diffraction source/receiver this close to the edge: degenerate
-constexpr double kUtdEpsD = 1e-8;   // shadow-boundary switch of cot*F (binary64)
-constexpr float kUtdEpsF = 1e-4f;   // same, binary32
+constexpr double kUtdEpsD = 1e-8;   // shadow-boundary switch of cot*F (|eps| formed in the geometry type)
 
 template <class F> struct ChainOut {
   V3<F> Q[DRT_MAX_INT];
@@ -265,35 +264,43 @@ template <class F> DRT_HD Cx<F> utd_transition(F X) {
   return cdiv(cx<F>(F(0), X), t);
 }
 
-template <class F> DRT_HD Cx<F> cot_F(F beta, F sgn, F n, F kL) {
+// cot((pi + sgn*beta)/(2n)) F(kL a^sgn(beta)) of the Kouyoumjian-Pathak coefficient.  With
+// N the integer nearest (beta + sgn*pi)/(2 pi n) and eps = pi + sgn*(beta - 2 pi n N), the
+// argument of the cotangent is pi N' + eps/(2n) and a^sgn(beta) = 2 cos^2((2 pi n N - beta)/2)
+// = 2 sin^2(eps/2), so both are evaluated from eps (formed in the geometry type F) without
+// the cancellation of the textbook form near a shadow or reflection boundary; below
+// |eps| = 1e-8 the product is replaced by its small-eps limit.
+template <class F, class G> DRT_HD Cx<G> cot_F(F beta, F sgn, F n, G kL) {
   const F pi = Consts<F>::pi;
   F N = mrint((beta + sgn * pi) / (F(2) * pi * n));
-  F eps = pi + sgn * beta - sgn * F(2) * pi * n * N;
-  const F lim = sizeof(F) == 8 ? F(kUtdEpsD) : F(kUtdEpsF);
-  if (mfabs(eps) < lim) {
-    F sg = eps > F(0) ? F(1) : (eps < F(0) ? F(-1) : F(0));
-    const F r2 = F(0.70710678118654752);
-    Cx<F> w = cx<F>(r2, r2);                                // e^{j pi/4}
-    Cx<F> inner = cx<F>(msqrt(F(2) * pi * kL) * sg, F(0)) - (F(2) * kL * eps) * w;
-    return n * (inner * w);
+  F epsF = pi + sgn * beta - sgn * F(2) * pi * n * N;
+  G eps = G(epsF), nn = G(n);
+  if (mfabs(epsF) < F(kUtdEpsD)) {
+    G sg = eps > G(0) ? G(1) : (eps < G(0) ? G(-1) : G(0));
+    const G r2 = G(0.70710678118654752);
+    Cx<G> w = cx<G>(r2, r2);                                // e^{j pi/4}
+    Cx<G> inner = cx<G>(msqrt(G(2) * Consts<G>::pi * kL) * sg, G(0)) - (G(2) * kL * eps) * w;
+    return nn * (inner * w);
   }
-  F c = mcos((F(2) * n * pi * N - beta) * F(0.5));
-  F a = F(2) * c * c;
-  Cx<F> fx = utd_transition(kL * a);
-  F ct = F(1) / mtan((pi + sgn * beta) / (F(2) * n));
+  G h = msin(eps * G(0.5));
+  Cx<G> fx = utd_transition(kL * (G(2) * h * h));
+  G ct = G(1) / mtan(eps / (G(2) * nn));
   return ct * fx;
 }
 
-// Kouyoumjian-Pathak coefficient of a perfectly conducting wedge (soft for pol 0, hard for 1).
-template <class F> DRT_HD Cx<F> utd_coefficient(F phi, F phi_p, F sin_b0, F n, F k, F Ld, int pol) {
-  const F pi = Consts<F>::pi;
-  F bm = phi - phi_p, bp = phi + phi_p, kL = k * Ld;
-  Cx<F> tm = cot_F(bm, F(1), n, kL) + cot_F(bm, F(-1), n, kL);
-  Cx<F> tp = cot_F(bp, F(1), n, kL) + cot_F(bp, F(-1), n, kL);
-  Cx<F> sum = pol == DRT_PAR ? tm + tp : tm - tp;
-  const F r2 = F(0.70710678118654752);
-  F scale = F(1) / (F(2) * n * msqrt(F(2) * pi * k) * sin_b0);
-  Cx<F> pre = cx<F>(-r2 * scale, r2 * scale);                // -e^{-j pi/4} * scale
+// Kouyoumjian-Pathak coefficient of a perfectly conducting wedge (soft for pol 0, hard for 1);
+// angles in the geometry type F, the rest in the field type G.
+template <class F, class G>
+DRT_HD Cx<G> utd_coefficient(F phi, F phi_p, G sin_b0, F n, G k, G Ld, int pol) {
+  const G pi = Consts<G>::pi;
+  F bm = phi - phi_p, bp = phi + phi_p;
+  G kL = k * Ld;
+  Cx<G> tm = cot_F<F, G>(bm, F(1), n, kL) + cot_F<F, G>(bm, F(-1), n, kL);
+  Cx<G> tp = cot_F<F, G>(bp, F(1), n, kL) + cot_F<F, G>(bp, F(-1), n, kL);
+  Cx<G> sum = pol == DRT_PAR ? tm + tp : tm - tp;
+  const G r2 = G(0.70710678118654752);
+  G scale = G(1) / (G(2) * G(n) * msqrt(G(2) * pi * k) * sin_b0);
+  Cx<G> pre = cx<G>(-r2 * scale, r2 * scale);                // -e^{-j pi/4} * scale
   return pre * sum;
 }
 
@@ -326,9 +333,10 @@ template <class F> DRT_HD F er_norm_directive(int alpha, F cos_ti) {
 // ---------------------------------------------------------------------------------------
 // the whole per-(ray, instant) evaluation
 
-template <class F> struct RayResult {
-  F L, dop, aod_az, aod_el, aoa_az, aoa_el;
-  Cx<F> gain;
+template <class F, class G = F> struct RayResult {
+  F L, dop;
+  G aod_az, aod_el, aoa_az, aoa_el;
+  Cx<G> gain;
   bool ok, degen;
   V3<F> Q[DRT_MAX_INT];      // interaction points (used by the loader's t0 checks)
 };
@@ -338,13 +346,13 @@ template <class F> DRT_HD void dir_angles(V3<F> v, F& az, F& el) {
   el = matan2(v.z, msqrt(v.x * v.x + v.y * v.y));
 }
 
-// Evaluate one ray whose N interaction slots are already moved to the instant.
+// Evaluate one ray whose N interaction slots are already moved to the instant.  Geometry
+// (points, length, Doppler) is computed in F; angles and the field coefficient in G.
 // Template parameters fix the signature so that every array stays in registers.
-template <class F, int N, int DP, bool SCAT>
-DRT_HD RayResult<F> eval_ray(const SceneView& sc, const DRay& ray, const Slot<F>* sl, V3<F> TX,
-                             V3<F> VTX, V3<F> RX, V3<F> VRX, F f_c) {
-  const F pi = Consts<F>::pi;
-  RayResult<F> res;
+template <class F, class G, int N, int DP, bool SCAT>
+DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot<F>* sl, V3<F> TX,
+                                V3<F> VTX, V3<F> RX, V3<F> VRX, F f_c) {
+  RayResult<F, G> res;
   ChainOut<F> ch;
   if constexpr (SCAT) {
     ch.ok = true;
@@ -380,43 +388,45 @@ DRT_HD RayResult<F> eval_ray(const SceneView& sc, const DRay& ray, const Slot<F>
   }
   dLdt += dot(kh[N], VRX - uprev);
   res.dop = -(f_c / Consts<F>::c0) * dLdt;
-  dir_angles(kh[0], res.aod_az, res.aod_el);
-  dir_angles(-kh[N], res.aoa_az, res.aoa_el);
+  auto gv = [](V3<F> v) { return V3<G>{G(v.x), G(v.y), G(v.z)}; };
+  dir_angles(gv(kh[0]), res.aod_az, res.aod_el);
+  dir_angles(gv(-kh[N]), res.aoa_az, res.aoa_el);
   res.L = L;
 
-  const F lam = Consts<F>::c0 / f_c;
-  Cx<F> gam = cx<F>(F(1), F(0));
+  const G pi = Consts<G>::pi;
+  const G lam = G(Consts<F>::c0 / f_c);
+  Cx<G> gam = cx<G>(G(1), G(0));
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     if (SCAT || i == DP) continue;
     const DPlane& pl = sc.planes[ray.prim[i]];
-    F ct = mfabs(dot(kh[i], sl[i].n));
-    gam = gam * fresnel<F>(ct, sc.mats[pl.mat], lam, ray.pol[i]);
+    G ct = G(mfabs(dot(kh[i], sl[i].n)));
+    gam = gam * fresnel<G>(ct, sc.mats[pl.mat], lam, ray.pol[i]);
   }
   bool ok = ch.ok;
-  Cx<F> a;
+  Cx<G> a;
   if constexpr (SCAT) {
     const DTile& tl = sc.tiles[ray.prim[0]];
     V3<F> n = sl[0].n;
     F cti = -dot(kh[0], n), cts = dot(kh[1], n);
     ok = ok && cti > F(0) && cts > F(0);
     V3<F> spec = kh[0] - (F(2) * dot(kh[0], n)) * n;
-    F cpsi = dot(spec, kh[1]);
-    F amp;
-    F ci = ok ? cti : F(1), cs = ok ? cts : F(1);
+    G cpsi = G(dot(spec, kh[1]));
+    G amp;
+    G ci = ok ? G(cti) : G(1), cs = ok ? G(cts) : G(1);
     if (tl.model == 0) {
-      amp = F(tl.S) * msqrt(F(tl.area) * ci * cs / pi);
+      amp = G(tl.S) * msqrt(G(tl.area) * ci * cs / pi);
     } else {
-      F x = (F(1) + cpsi) * F(0.5);
-      if (x < F(0)) x = F(0);
-      F lobe = F(1);
+      G x = (G(1) + cpsi) * G(0.5);
+      if (x < G(0)) x = G(0);
+      G lobe = G(1);
       for (int j = 0; j < tl.alpha / 2; ++j) lobe *= x;
       if (tl.alpha & 1) lobe *= msqrt(x);
-      amp = F(tl.S) * msqrt(F(tl.area) * ci / er_norm_directive<F>(tl.alpha, ci)) * lobe;
+      amp = G(tl.S) * msqrt(G(tl.area) * ci / er_norm_directive<G>(tl.alpha, ci)) * lobe;
     }
-    F ph = F(tl.phase0);
-    F sc_ = lam / (F(4) * pi) * amp / (len[0] * len[1]);
-    a = cx<F>(sc_ * mcos(ph), sc_ * msin(ph));
+    G ph = G(tl.phase0);
+    G sc_ = lam / (G(4) * pi) * amp / (G(len[0]) * G(len[1]));
+    a = cx<G>(sc_ * mcos(ph), sc_ * msin(ph));
   } else if constexpr (DP >= 0) {
     const DEdge& ed = sc.edges[ray.prim[DP]];
     const Slot<F>& es = sl[DP];
@@ -428,21 +438,23 @@ DRT_HD RayResult<F> eval_ray(const SceneView& sc, const DRay& ray, const Slot<F>
     F sb = msqrt(sb2 > F(0) ? sb2 : F(0));
     V3<F> up = dA - dot(dA, es.e) * es.e;
     V3<F> uo = dB - dot(dB, es.e) * es.e;
+    const F piF = Consts<F>::pi;
     F phi_p = matan2(dot(up, es.n), dot(up, es.t));
     F phi = matan2(dot(uo, es.n), dot(uo, es.t));
-    if (phi_p < F(0)) phi_p += F(2) * pi;
-    if (phi < F(0)) phi += F(2) * pi;
-    F Ld = s * sp * sb * sb / (s + sp);
-    F k = F(2) * pi / lam;
-    Cx<F> D = utd_coefficient<F>(phi, phi_p, sb, F(ed.wn), k, Ld, ray.pol[DP]);
-    F scale = lam / (F(4) * pi) / msqrt(sp * s * (sp + s));
+    if (phi_p < F(0)) phi_p += F(2) * piF;
+    if (phi < F(0)) phi += F(2) * piF;
+    G Ld = G(s * sp * sb * sb / (s + sp));
+    G k = G(2) * pi / lam;
+    Cx<G> D = utd_coefficient<F, G>(phi, phi_p, G(sb), F(ed.wn), k, Ld, ray.pol[DP]);
+    G scale = lam / (G(4) * pi) / G(msqrt(sp * s * (sp + s)));
     a = scale * (gam * D);
   } else {
-    a = (lam / (F(4) * pi * L)) * gam;
+    a = (lam / (G(4) * pi * G(L))) * gam;
   }
   if (!ok) {
-    res.L = res.dop = res.aod_az = res.aod_el = res.aoa_az = res.aoa_el = F(0);
-    a = cx<F>(F(0), F(0));
+    res.L = res.dop = F(0);
+    res.aod_az = res.aod_el = res.aoa_az = res.aoa_el = G(0);
+    a = cx<G>(G(0), G(0));
   }
   res.gain = a;
   res.ok = ok;

@@ -43,6 +43,10 @@ struct RecM { float ar, ai, phi0, phiB, phi1, pad; };   // split, MFMA path: 24 
 struct RecD { double L, gr, gi, zr, zi; };              // binary64: 40 B
 struct RecN { float L, gr, gi, zr, zi, pad; };          // naive binary32: 24 B
 
+// Field-coefficient and angle type of a precision: binary64 only in DRT_FP64.
+template <int PREC> struct GainT { using type = float; };
+template <> struct GainT<DRT_FP64> { using type = double; };
+
 template <class F, int MODE, int PREC, int CLS>
 __global__ __launch_bounds__(256) void k_geom(SceneView sc, const int32_t* order, int count,
                                               const typename Vec2<F>::type* pose, int T, double dt, double f_c,
@@ -74,8 +78,9 @@ __global__ __launch_bounds__(256) void k_geom(SceneView sc, const int32_t* order
     }
   }
   F fc = F(f_c);
-  RayResult<F> res = with_signature_in<F, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
-    return eval_ray<F, N, DP, SCAT>(sc, ray, sl, TX, VTX, RX, VRX, fc);
+  using G = typename GainT<PREC>::type;
+  RayResult<F, G> res = with_signature_in<F, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
+    return eval_ray<F, G, N, DP, SCAT>(sc, ray, sl, TX, VTX, RX, VRX, fc);
   });
 
   if constexpr (MODE == GEOM_EXTRAP) {
@@ -107,7 +112,7 @@ __global__ __launch_bounds__(256) void k_geom(SceneView sc, const int32_t* order
     reinterpret_cast<RecM*>(rec)[o] = {float(res.gain.re), float(res.gain.im), float(p0), float(pB), float(p1), 0.f};
   } else {
     size_t o = (size_t(chunk) * n_rays + r) * 64 + lane;
-    if (!active) res.gain = cx<F>(F(0), F(0));
+    if (!active) res.gain = cx<G>(G(0), G(0));
     const double df_over_c = ap.f1c;
     if constexpr (PREC == DRT_FP64) {
       double cz = double(res.L) * df_over_c;

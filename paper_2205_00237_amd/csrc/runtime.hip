@@ -185,7 +185,7 @@ template <int N, int DP, bool SCAT>
 static RayResult<double> eval_host(const SceneView& sc, const DRay& ray, const Slot<double>* sl) {
   V3<double> TX = ld3<double>(sc.tx_p), RX = ld3<double>(sc.rx_p);
   V3<double> VTX = ld3<double>(sc.tx_v), VRX = ld3<double>(sc.rx_v);
-  return eval_ray<double, N, DP, SCAT>(sc, ray, sl, TX, VTX, RX, VRX, 1e9);
+  return eval_ray<double, double, N, DP, SCAT>(sc, ray, sl, TX, VTX, RX, VRX, 1e9);
 }
 
 static int validate_and_pack(const drt_scene_desc* d, Scene& s) {

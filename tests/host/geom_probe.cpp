@@ -24,8 +24,14 @@ int main() {
       double phi, php, sb, n, k, Ld;
       int pol;
       std::scanf("%lf %lf %lf %lf %lf %lf %d", &phi, &php, &sb, &n, &k, &Ld, &pol);
-      Cx<double> v = utd_coefficient<double>(phi, php, sb, n, k, Ld, pol);
+      Cx<double> v = utd_coefficient<double, double>(phi, php, sb, n, k, Ld, pol);
       std::printf("%.17g %.17g\n", v.re, v.im);
+    } else if (!std::strcmp(fn, "D32")) {   // binary64 angles, binary32 field arithmetic
+      double phi, php, sb, n, k, Ld;
+      int pol;
+      std::scanf("%lf %lf %lf %lf %lf %lf %d", &phi, &php, &sb, &n, &k, &Ld, &pol);
+      Cx<float> v = utd_coefficient<double, float>(phi, php, float(sb), n, float(k), float(Ld), pol);
+      std::printf("%.9g %.9g\n", v.re, v.im);
     } else if (!std::strcmp(fn, "G64")) {
       double ct, er, sg, lam;
       int pec, pol;

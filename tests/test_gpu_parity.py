@@ -2,6 +2,7 @@
 
 Tolerances: binary64 mode |dL| <= 1e-9 m (path length), |dH| / rms(H) <= 1e-6, gains
 relative 1e-9, Doppler and angles within their binary32 output rounding; split mode
+path length and Doppler as binary64, gains 1e-5 relative, angles 1e-6 rad,
 |H| within 1e-4 relative and arg H within 1e-3 rad on every (t, f) where |H_ref| is at
 least 0.1 rms(|H_ref|) (a relative error is meaningless in deep fades), and
 |dH| / rms(H) <= 1e-4 everywhere."""
@@ -45,7 +46,7 @@ def h_errors(H, Href):
     return e_all, e_mag, e_arg
 
 
-def check_extrapolation(out, ref, prec, where):
+def check_extrapolation(out, ref, prec, where, f_c):
     from paper_2205_00237_amd.drt import DRT_FP64
     v = out["valid"].cpu().numpy().astype(bool)
     assert np.array_equal(v, ref["valid"]), f"{where}: valid flags differ at {np.argwhere(v != ref['valid'])[:5]}"
@@ -58,12 +59,22 @@ def check_extrapolation(out, ref, prec, where):
         a = out[k].cpu().numpy().astype(np.float64)
         d = np.abs(a - ref[k])
         d = np.minimum(d, 2 * math.pi - d)   # +-pi azimuth wrap
-        assert (d <= 1e-9 + np.abs(ref[k]) * 2.0 ** -23).all(), f"{where}: {k} {d.max()}"
+        # binary64 angles rounded once to binary32; split mode forms them in binary32
+        tol = 1e-9 + np.abs(ref[k]) * 2.0 ** -23 if prec == DRT_FP64 else 1e-6
+        assert (d <= tol).all(), f"{where}: {k} {d.max()}"
     g = out["gain"].cpu().numpy().astype(np.complex128)
     gr = ref["gain"]
     scale = np.abs(gr).max()
-    rel = 1e-9 if prec == DRT_FP64 else 2.0 ** -23
-    assert (np.abs(g - gr) <= rel * np.abs(gr) + 1e-12 * scale).all(), \
+    if prec == DRT_FP64:
+        tol = 1e-9 * np.abs(gr) + 1e-12 * scale
+    else:
+        # split mode evaluates the field coefficient in binary32 from binary64 geometry: 1e-5
+        # relative, or 3e-6 of the free-space amplitude lambda/(4 pi L) of the same path where
+        # the four diffraction terms (each at most n sqrt(2 pi k L) in size) cancel to a weak
+        # coefficient
+        fs = (C0 / f_c) / (4 * math.pi * np.maximum(ref["L"], 1e-30))
+        tol = 1e-5 * np.abs(gr) + 3e-6 * fs + 1e-12 * scale
+    assert (np.abs(g - gr) <= tol).all(), \
         f"{where}: gain {(np.abs(g - gr) / np.maximum(np.abs(gr), 1e-300)).max()}"
 
 
@@ -75,7 +86,7 @@ def test_config1_extrapolate_and_cfr(ctx, precision):
     sid = ctx.load_scene(s)
     ref, Href = oracle.run(s, tg, fg)
     out = ctx.extrapolate(sid, tg, fg.f_c, precision)
-    check_extrapolation(out, ref, precision, "config1")
+    check_extrapolation(out, ref, precision, "config1", fg.f_c)
     H = ctx.cfr(sid, tg, fg, precision).cpu().numpy()
     e_all, e_mag, e_arg = h_errors(H.astype(np.complex128), Href)
     say(f"  H errors: all {e_all:.3g} mag {e_mag:.3g} arg {e_arg:.3g}")
@@ -96,7 +107,7 @@ def test_ragged_shapes(ctx, T, K, nr):
     ref, Href = oracle.run(s, tg, fg, rays=np.arange(nr))
     for prec in (0, 1):
         out = ctx.extrapolate(sid, tg, fg.f_c, prec, n_rays=nr)
-        check_extrapolation(out, ref, prec, f"ragged{T, K, nr}")
+        check_extrapolation(out, ref, prec, f"ragged{T, K, nr}", fg.f_c)
         H = ctx.cfr(sid, tg, fg, prec, n_rays=nr).cpu().numpy().astype(np.complex128)
         e_all, e_mag, e_arg = h_errors(H, Href)
         assert e_all <= (1e-6 if prec == 0 else 1e-4), (prec, e_all)
@@ -126,7 +137,7 @@ def test_config2_full_size(ctx):
     out = ctx.extrapolate(sid, tg, fg.f_c, 0)
     say("  oracle geometry at every instant ...")
     ref = oracle.extrapolate(s, np.arange(tg.n_steps) * tg.dt, fg.f_c)
-    check_extrapolation(out, ref, 0, "config2")
+    check_extrapolation(out, ref, 0, "config2", fg.f_c)
     for prec in (0, 1):
         H = ctx.cfr(sid, tg, fg, prec).cpu().numpy().astype(np.complex128)[rows]
         e_all, e_mag, e_arg = h_errors(H, Href)
@@ -147,7 +158,7 @@ def test_config3_scattering(ctx):
     ref, Href = oracle.run(s, tg, fg)
     for prec in (0, 1):
         out = ctx.extrapolate(sid, tg, fg.f_c, prec)
-        check_extrapolation(out, ref, prec, "config3")
+        check_extrapolation(out, ref, prec, "config3", fg.f_c)
         H = ctx.cfr(sid, tg, fg, prec).cpu().numpy().astype(np.complex128)
         e_all, e_mag, e_arg = h_errors(H, Href)
         say(f"  prec {prec}: H errors all {e_all:.3g} mag {e_mag:.3g} arg {e_arg:.3g}")

@@ -178,9 +178,11 @@ int drt_poll(drt_ctx *ctx, uint64_t ticket, drt_req_stat *stat);
 double drt_now(void);
 
 /* Kernel timing (tracing aid).  While enabled, drt_extrapolate and drt_cfr record a
- * hipEvent pair around each kernel they launch, on the caller's stream, so the figures are
- * device durations of those kernels alone.  drt_profile_read waits for the recorded events
- * and returns the totals since the last reset; index with enum drt_kernel_id. */
+ * hipEvent pair around each kernel they launch, on the caller's stream (around the
+ * back-to-back per-signature-class kernels of the geometry step together), so the figures
+ * are device durations of those kernels alone.  drt_profile_read waits for the recorded
+ * events and returns the totals since the last reset; index with enum drt_kernel_id.
+ * launches counts kernels, so ms / launches is the mean duration of one kernel. */
 enum drt_kernel_id { DRT_K_POSE = 0, DRT_K_GEOM = 1, DRT_K_CFR = 2, DRT_K_REDUCE = 3, DRT_K_COUNT = 4 };
 typedef struct {
   double ms[DRT_K_COUNT];          /* summed device milliseconds per kernel */

@@ -348,8 +348,10 @@ template <class F> DRT_HD void dir_angles(V3<F> v, F& az, F& el) {
 
 // Evaluate one ray whose N interaction slots are already moved to the instant.  Geometry
 // (points, length, Doppler) is computed in F; angles and the field coefficient in G.
-// Template parameters fix the signature so that every array stays in registers.
-template <class F, class G, int N, int DP, bool SCAT>
+// Template parameters fix the signature so that every array stays in registers; the
+// interaction points are copied out only with KEEP_Q (the loader's t0 checks), since the
+// copy would otherwise survive in private memory behind the signature dispatch.
+template <class F, class G, int N, int DP, bool SCAT, bool KEEP_Q = false>
 DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot<F>* sl, V3<F> TX,
                                 V3<F> VTX, V3<F> RX, V3<F> VRX, F f_c) {
   RayResult<F, G> res;
@@ -459,8 +461,10 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
   res.gain = a;
   res.ok = ok;
   res.degen = ch.degen;
+  if constexpr (KEEP_Q) {
 #pragma unroll
-  for (int i = 0; i < N; ++i) res.Q[i] = ch.Q[i];
+    for (int i = 0; i < N; ++i) res.Q[i] = ch.Q[i];
+  }
   return res;
 }
 

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_pose(const DBody* bodies, int nb, int T
 // ---------------------------------------------------------------------------------------
 
 struct RecS { double L; float gr, gi, zr, zi; };       // split: 24 B
-struct RecM { float ar, ai, phi0, phiB, phi1, pad; };   // split, MFMA path: 24 B (phases in cycles)
+struct RecM { float amp, phi0, phiB, phi1; };          // split, MFMA path: 16 B (phases in cycles)
 struct RecD { double L, gr, gi, zr, zi; };              // binary64: 40 B
 struct RecN { float L, gr, gi, zr, zi, pad; };          // naive binary32: 24 B
 
@@ -101,15 +101,18 @@ __global__ __launch_bounds__(256) void k_geom(SceneView sc, const int32_t* order
     if (eo.valid) eo.valid[o] = res.ok ? 1 : 0;
   } else if constexpr (MODE == GEOM_ANCHOR_MFMA) {
     // phases of the first subcarrier, of one row block and of one subcarrier, each reduced
-    // modulo one cycle in binary64 before rounding to binary32
+    // modulo one cycle in binary64 before rounding to binary32; the gain enters as its
+    // modulus and its argument, the latter folded into the first-subcarrier phase
+    // (a e^{-j 2 pi p0} = |a| e^{-j 2 pi (p0 - arg a / 2 pi)})
     if (!active) return;
     size_t o = size_t(t) * n_rays + r;      // instant-major: a ray-sum wave streams its instant
     double L = double(res.L);
-    double p0 = L * ap.f0c, pB = L * ap.fBc, p1 = L * ap.f1c;
+    const float gr = float(res.gain.re), gi = float(res.gain.im);
+    double p0 = L * ap.f0c - double(atan2f(gi, gr)) * (0.5 / M_PI), pB = L * ap.fBc, p1 = L * ap.f1c;
     p0 -= floor(p0);
     pB -= floor(pB);
     p1 -= floor(p1);
-    reinterpret_cast<RecM*>(rec)[o] = {float(res.gain.re), float(res.gain.im), float(p0), float(pB), float(p1), 0.f};
+    reinterpret_cast<RecM*>(rec)[o] = {sqrtf(gr * gr + gi * gi), float(p0), float(pB), float(p1)};
   } else {
     size_t o = (size_t(chunk) * n_rays + r) * 64 + lane;
     if (!active) res.gain = cx<G>(G(0), G(0));
@@ -253,8 +256,9 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // accumulator rows 4(l/16)..4(l/16)+3 of column l%16.  Rows are k1 (MT tiles of 16), columns
 // are [C_re for k2 < B | C_im for k2 < B] (NT tiles of 16, B = 8 NT).  Operands are
 // generated on the vector ALU from the record's binary64-reduced phases: the U row phase
-// phi0 + k1 phiB and the V column phase k2 phi1 (cycles, k1, k2 < 64) are formed in binary32
-// and fed to v_sin/v_cos, which take revolutions.
+// phi0 + k1 phiB and the V column phase k2 phi1 (cycles, k1, k2 < 64, so below 65) are
+// formed in binary32 and fed to v_sin/v_cos, which take revolutions and reduce them modulo
+// one exactly over [-256, 256].
 template <int MT, int NT>
 __global__ __launch_bounds__(256) void k_cfr_mfma(const RecM* rec, CfrArgs a, float* out) {
   constexpr int B = 8 * NT;
@@ -278,7 +282,7 @@ __global__ __launch_bounds__(256) void k_cfr_mfma(const RecM* rec, CfrArgs a, fl
   // current one is consumed pair by pair through cross-lane shuffles
   auto load = [&](int rb) {
     int r = rb + lane;
-    return r < r1 ? rt[r] : RecM{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    return r < r1 ? rt[r] : RecM{0.f, 0.f, 0.f, 0.f};
   };
   RecM cur = load(r0);
   for (int rb = r0; rb < r1; rb += 64) {
@@ -288,27 +292,26 @@ __global__ __launch_bounds__(256) void k_cfr_mfma(const RecM* rec, CfrArgs a, fl
     for (int p = 0; p < npairs; ++p) {
     const int src = 2 * p + rsel;
     RecM q;
-    q.ar = __shfl(cur.ar, src);
-    q.ai = __shfl(cur.ai, src);
+    q.amp = __shfl(cur.amp, src);
     q.phi0 = __shfl(cur.phi0, src);
     q.phiB = __shfl(cur.phiB, src);
     q.phi1 = __shfl(cur.phi1, src);
     float av[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      float ph = __builtin_amdgcn_fractf(__builtin_fmaf(float(mt * 16 + m), q.phiB, q.phi0));
+      float ph = __builtin_fmaf(float(mt * 16 + m), q.phiB, q.phi0);
       float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
-      av[mt] = part == 0 ? q.ar * c + q.ai * s : q.ai * c - q.ar * s;   // Re / Im of a e^{-j 2 pi ph}
+      av[mt] = part == 0 ? q.amp * c : -(q.amp * s);                     // Re / Im of |a| e^{-j 2 pi ph}
     }
     float bv[NT];
     if constexpr (NT == 1) {
-      float ph = __builtin_amdgcn_fractf(float(m & 7) * q.phi1);
+      float ph = float(m & 7) * q.phi1;
       float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
       bv[0] = (m >> 3) == 0 ? (part == 0 ? c : s) : (part == 0 ? -s : c);
     } else {
 #pragma unroll
       for (int h = 0; h < NT / 2; ++h) {
-        float ph = __builtin_amdgcn_fractf(float(h * 16 + m) * q.phi1);
+        float ph = float(h * 16 + m) * q.phi1;
         float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
         bv[h] = part == 0 ? c : s;                 // C_re columns: V_re, -V_im
         bv[h + NT / 2] = part == 0 ? -s : c;       // C_im columns: V_im, V_re
@@ -358,15 +361,38 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // hi + lo binary16 pairs of two binary32 values, each pair packed in one 32-bit word: hi
 // rounds toward zero, lo = x - hi is representable to 2^-11 of itself, so hi + lo keeps
 // ~22 bits of x.
-__device__ __forceinline__ void split_pair(float x, float y, unsigned& hi, unsigned& lo) {
-  fp16x2 h = __builtin_amdgcn_cvt_pkrtz(x, y);
-  fp16x2 l = __builtin_amdgcn_cvt_pkrtz(x - float(h[0]), y - float(h[1]));
-  hi = __builtin_bit_cast(unsigned, h);
-  lo = __builtin_bit_cast(unsigned, l);
+// The residuals x - hi are exact in binary32 (hi keeps the leading 11 bits of x) and are
+// formed by one mixed-precision FMA each, -hi * 1 + x, reading hi straight from its half of
+// the packed word; the compiler lowers the plain expression to a conversion and a subtraction.
+__device__ __forceinline__ float resid_lo(unsigned h, float x) {
+  float r;
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(x));
+  return r;
+}
+__device__ __forceinline__ float resid_hi(unsigned h, float x) {
+  float r;
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(x));
+  return r;
+}
+__device__ __forceinline__ unsigned pk16(float x, float y) {
+  return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(x, y));
 }
 
-// (p, q) -> (-q, p) on a packed binary16 pair: swap the halves, flip the new low sign
-__device__ __forceinline__ unsigned rot_pair(unsigned w) { return ((w >> 16) | (w << 16)) ^ 0x8000u; }
+// (x, y) -> hi, lo words of (x, y); with rot, also those of (-y, x): rounding toward zero
+// commutes with negation, so the rotated pair splits into the rotated halves
+struct Split16 { unsigned hi, lo, rhi, rlo; };
+template <bool ROT>
+__device__ __forceinline__ Split16 split_pair(float x, float y) {
+  Split16 w;
+  w.hi = pk16(x, y);
+  const float rx = resid_lo(w.hi, x), ry = resid_hi(w.hi, y);
+  w.lo = pk16(rx, ry);
+  if constexpr (ROT) {
+    w.rhi = pk16(-y, x);
+    w.rlo = pk16(-ry, rx);
+  }
+  return w;
+}
 
 // Split-precision ray sum on the binary16 matrix cores.  Same factorisation as k_cfr_mfma
 // (H[k1 B + k2] = sum_r U[k1][r] V[r][k2]), but each binary32 operand x is carried as
@@ -399,13 +425,10 @@ __global__ __launch_bounds__(256) void k_cfr_mfma16(const RecM* rec, CfrArgs a, 
 
   auto load = [&](int rb) {
     int r = rb + lane;
-    return r < r1 ? rt[r] : RecM{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    return r < r1 ? rt[r] : RecM{0.f, 0.f, 0.f, 0.f};
   };
   float amax = 0.f;
-  for (int rb = r0; rb < r1; rb += 64) {
-    RecM q = load(rb);
-    amax = fmaxf(amax, fmaxf(fabsf(q.ar), fabsf(q.ai)));
-  }
+  for (int rb = r0 + lane; rb < r1; rb += 64) amax = fmaxf(amax, rt[rb].amp);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
   int e2 = 0;
@@ -421,39 +444,33 @@ __global__ __launch_bounds__(256) void k_cfr_mfma16(const RecM* rec, CfrArgs a, 
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int src = bk * 16 + grp * 4 + j;
-        const float ar = __shfl(cur.ar, src) * kScale, ai = __shfl(cur.ai, src) * kScale;
+        const float amp = __shfl(cur.amp, src) * kScale;
         const float phi0 = __shfl(cur.phi0, src), phiB = __shfl(cur.phiB, src), phi1 = __shfl(cur.phi1, src);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          float ph = __builtin_amdgcn_fractf(__builtin_fmaf(float(mt * 16 + m), phiB, phi0));
+          float ph = __builtin_fmaf(float(mt * 16 + m), phiB, phi0);
           float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
-          unsigned h, l;
-          split_pair(ar * c + ai * s, ai * c - ar * s, h, l);   // U = a e^{-j 2 pi ph}
-          ahw[mt][j] = h;
-          alw[mt][j] = l;
+          Split16 w = split_pair<false>(amp * c, -(amp * s));   // U = |a| e^{-j 2 pi ph}
+          ahw[mt][j] = w.hi;
+          alw[mt][j] = w.lo;
         }
         if constexpr (NT == 1) {
-          float ph = __builtin_amdgcn_fractf(float(m & 7) * phi1);
+          float ph = float(m & 7) * phi1;
           float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
-          unsigned h, l;
-          split_pair(c, s, h, l);                     // C_re column: (V_re, -V_im)
-          if ((m >> 3) != 0) {                        // C_im column: (V_im, V_re)
-            h = rot_pair(h);
-            l = rot_pair(l);
-          }
-          bhw[0][j] = h;
-          blw[0][j] = l;
+          // C_re column: (V_re, -V_im) = (c, s); C_im column: (V_im, V_re) = (-s, c)
+          Split16 w = (m >> 3) == 0 ? split_pair<false>(c, s) : split_pair<false>(-s, c);
+          bhw[0][j] = w.hi;
+          blw[0][j] = w.lo;
         } else {
 #pragma unroll
           for (int hh = 0; hh < NT / 2; ++hh) {
-            float ph = __builtin_amdgcn_fractf(float(hh * 16 + m) * phi1);
+            float ph = float(hh * 16 + m) * phi1;
             float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
-            unsigned h, l;
-            split_pair(c, s, h, l);
-            bhw[hh][j] = h;
-            blw[hh][j] = l;
-            bhw[hh + NT / 2][j] = rot_pair(h);
-            blw[hh + NT / 2][j] = rot_pair(l);
+            Split16 w = split_pair<true>(c, s);
+            bhw[hh][j] = w.hi;
+            blw[hh][j] = w.lo;
+            bhw[hh + NT / 2][j] = w.rhi;
+            blw[hh + NT / 2][j] = w.rlo;
           }
         }
       }

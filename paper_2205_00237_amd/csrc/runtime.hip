@@ -109,7 +109,7 @@ struct drt_ctx {
   int split_path = CFR_MFMA16;               // ray-sum kernel of DRT_SPLIT (DRT_CFR_KERNEL)
 
   // kernel timing
-  struct ProfRec { int kernel; hipEvent_t a, b; };
+  struct ProfRec { int kernel, n; hipEvent_t a, b; };   // n kernels back to back between a and b
   std::atomic<bool> prof{false};
   std::mutex prof_mu;
   std::vector<ProfRec> prof_recs;
@@ -185,7 +185,7 @@ template <int N, int DP, bool SCAT>
 static RayResult<double> eval_host(const SceneView& sc, const DRay& ray, const Slot<double>* sl) {
   V3<double> TX = ld3<double>(sc.tx_p), RX = ld3<double>(sc.rx_p);
   V3<double> VTX = ld3<double>(sc.tx_v), VRX = ld3<double>(sc.rx_v);
-  return eval_ray<double, double, N, DP, SCAT>(sc, ray, sl, TX, VTX, RX, VRX, 1e9);
+  return eval_ray<double, double, N, DP, SCAT, true>(sc, ray, sl, TX, VTX, RX, VRX, 1e9);
 }
 
 static int validate_and_pack(const drt_scene_desc* d, Scene& s) {
@@ -378,6 +378,13 @@ static RayClasses classes(const Scene& s, int n_rays) {
   return rc;
 }
 
+// geometry kernels one launch makes (one per non-empty signature class)
+static int class_kernels(const RayClasses& rc, int T) {
+  int n = 0;
+  for (int c = 0; c < CLS_COUNT; ++c) n += rc.count[c] > 0 && T > 0;
+  return n;
+}
+
 // ---------------------------------------------------------------------------------------
 // pipelines
 
@@ -402,9 +409,9 @@ static SceneView device_view(const Scene& s) {
 
 // Launch `fn` on stream st, bracketed by a hipEvent pair when kernel timing is on.
 template <class Fn>
-static hipError_t timed(drt_ctx* c, int kernel, hipStream_t st, Fn&& fn) {
+static hipError_t timed(drt_ctx* c, int kernel, hipStream_t st, Fn&& fn, int n_kernels = 1) {
   if (!c || !c->prof.load()) return fn();
-  drt_ctx::ProfRec r{kernel, nullptr, nullptr};
+  drt_ctx::ProfRec r{kernel, n_kernels, nullptr, nullptr};
   hipError_t e;
   if ((e = hipEventCreate(&r.a)) != hipSuccess) return e;
   if ((e = hipEventCreate(&r.b)) != hipSuccess) return e;
@@ -447,10 +454,11 @@ static int run_cfr(drt_ctx* c, const Scene& s, int n_rays, const drt_time_grid* 
   const double inv_c = 1.0 / 299792458.0;
   AnchorParams ap{p.a.f0 * inv_c, double(p.a.B) * p.a.df * inv_c, p.a.df * inv_c};
   int mode = p.a.path == CFR_VALU ? GEOM_ANCHOR : GEOM_ANCHOR_MFMA;
+  const RayClasses rc = classes(s, n_rays);
   HIP_OK(timed(c, DRT_K_GEOM, st, [&] {
-    return launch_geom(device_view(s), classes(s, n_rays), base + p.pose_off, T, tg->dt, fg->f_c, n_rays, prec,
+    return launch_geom(device_view(s), rc, base + p.pose_off, T, tg->dt, fg->f_c, n_rays, prec,
                        mode, none, base + p.rec_off, ap, st);
-  }));
+  }, class_kernels(rc, T)));
   if (p.a.G > 1) {
     HIP_OK(timed(c, DRT_K_CFR, st, [&] { return launch_cfr(base + p.rec_off, p.a, prec, base + p.part_off, st); }));
     HIP_OK(timed(c, DRT_K_REDUCE, st, [&] {
@@ -706,10 +714,11 @@ int drt_extrapolate(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_g
     return launch_pose((const DBody*)s->d_bodies.p, s->view.n_bodies, T, tg->dt, prec, sc.buf.p, hs);
   }));
   ExtrapOut eo{out->L, out->dop, out->aod_az, out->aod_el, out->aoa_az, out->aoa_el, out->gain, out->valid};
+  const RayClasses rc = classes(*s, n_rays);
   HIP_OK(timed(c, DRT_K_GEOM, hs, [&] {
-    return launch_geom(device_view(*s), classes(*s, n_rays), sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_EXTRAP,
+    return launch_geom(device_view(*s), rc, sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_EXTRAP,
                        eo, nullptr, AnchorParams{0.0, 0.0, 0.0}, hs);
-  }));
+  }, class_kernels(rc, T)));
   return DRT_OK;
 }
 
@@ -751,7 +760,7 @@ int drt_profile_read(drt_ctx* c, drt_profile* out, int reset) {
     float ms = 0.f;
     HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
     out->ms[r.kernel] += ms;
-    out->launches[r.kernel] += 1;
+    out->launches[r.kernel] += r.n;
   }
   if (reset) {
     for (auto& r : c->prof_recs) {

@@ -42,8 +42,11 @@ def test_hardware_sincos_on_revolutions():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2205_00237_amd import _abi
+    # the ray-sum kernels pass revolutions up to 65 without reducing them first
     x = np.concatenate([np.linspace(0, 1, 200001, dtype=np.float32),
-                        np.random.default_rng(1).random(100000).astype(np.float32)])
+                        np.random.default_rng(1).random(100000).astype(np.float32),
+                        np.random.default_rng(2).uniform(-70, 70, 100000).astype(np.float32),
+                        np.float32([-256, -65.75, 64.25, 65.0, 255.5, 256])])
     dx = torch.from_numpy(x).cuda()
     ds, dc = torch.empty_like(dx), torch.empty_like(dx)
     _abi.drt_probe_sincos_rev(dx.data_ptr(), x.size, ds.data_ptr(), dc.data_ptr())

@@ -84,16 +84,18 @@ def cpu_baseline(scene, tg, fg, budget_s=15.0):
                       f"({el:.1f} s, numpy float64, single thread)"}
 
 
-def serving(ctx, torch, n_requests):
-    """Config-5 mix: Poisson arrivals at 2000/s over 64 resident 20000-ray scenes."""
+def serving(ctx, torch, sids, n_requests, burst=False):
+    """Serving mix: Poisson arrivals at 2000/s over 64 resident 20000-ray scenes (burst: the
+    same kind of requests all submitted at once, which measures the served throughput)."""
     import numpy as np
     from paper_2205_00237_amd import scenes
     from paper_2205_00237_amd._abi import drt_now
     from paper_2205_00237_amd.drt import DRT_SPLIT
-    t = time.perf_counter()
-    sids = [ctx.load_scene(s) for s in scenes.config5_scenes()]
-    load_s = time.perf_counter() - t
     reqs = scenes.config5_requests(n_requests)
+    if burst:
+        for q in reqs:
+            q.arrival = 0.0
+    stats0 = ctx.serving_stats()
     pending, lat, samples, t_last = {}, [], 0, 0.0
     t_start = drt_now() + 0.05
     i = 0
@@ -117,17 +119,21 @@ def serving(ctx, torch, n_requests):
                 t_last = max(t_last, st[3])
         if i < len(reqs) and not pending:
             time.sleep(max(0.0, min(1e-4, t_start + reqs[i].arrival - drt_now())))
-    for s in sids:
-        ctx.unload_scene(s)
+    stats1 = ctx.serving_stats()
+    nb = stats1["batches"] - stats0["batches"]
     lat = np.array(lat)
     span = t_last - (t_start + reqs[0].arrival)
-    return {"workload": f"{len(reqs)} requests, Poisson 2000/s, 64 resident scenes of 20000 rays, "
+    arrivals = "all submitted at once" if burst else "Poisson 2000/s"
+    return {"workload": f"{len(reqs)} requests, {arrivals}, 64 resident scenes of 20000 rays, "
                         "rays log-uniform 50-20000, 10-1000 instants of 1 ms, 64-2048 subcarriers, "
                         "28/60 GHz, 400 MHz, split precision",
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "max_ms": float(lat.max() * 1e3), "samples_per_s": samples / span,
-            "offered_samples_per_s": samples / (reqs[-1].arrival - reqs[0].arrival),
-            "scene_load_s": load_s}
+            "offered_samples_per_s": (None if burst else samples / (reqs[-1].arrival - reqs[0].arrival)),
+            "graph_batches": nb,
+            "mean_batch": (stats1["batched_requests"] - stats0["batched_requests"]) / max(1, nb),
+            "max_batch": stats1["max_batch"],
+            "requests_alone": stats1["single_launches"] - stats0["single_launches"]}
 
 
 def main():
@@ -231,10 +237,20 @@ def main():
     ctx.unload_scene(sid)
     if not args.no_serving:
         log("serving mix ...")
-        out["serving"] = serving(ctx, torch, args.serving_requests)
+        from paper_2205_00237_amd import scenes as sc5
+        t = time.perf_counter()
+        sids = [ctx.load_scene(s) for s in sc5.config5_scenes()]
+        load5 = time.perf_counter() - t
+        out["serving"] = serving(ctx, torch, sids, args.serving_requests)
+        out["serving"]["scene_load_s"] = load5
+        log(f"serving: {out['serving']}")
+        log("serving burst ...")
+        out["serving_burst"] = serving(ctx, torch, sids, 512, burst=True)
+        log(f"serving burst: {out['serving_burst']}")
+        for s in sids:
+            ctx.unload_scene(s)
         out["p99_latency_ms"] = out["serving"]["p99_ms"]
         out["p50_latency_ms"] = out["serving"]["p50_ms"]
-        log(f"serving: {out['serving']}")
     ctx.close()
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")

@@ -164,15 +164,32 @@ int drt_extrapolate(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time
 int drt_cfr(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_grid *tg,
             const drt_freq_grid *fg, int32_t precision, void *H, void *stream);
 
-/* Serving: enqueue one channel-prediction request (continuous batching on internal
- * streams).  Non-blocking.  DRT_E_ADMISSION if its device footprint alone exceeds the
- * cap; otherwise it waits in the queue until memory frees up.  req->H is borrowed until
- * drt_poll reports done or an error. */
+/* Serving: enqueue one channel-prediction request.  Non-blocking.  DRT_E_ADMISSION if
+ * its device footprint alone exceeds the cap; otherwise it waits in the queue until a
+ * batch slot and memory free up.  A worker thread keeps up to four batches in flight, each
+ * on its own stream: a free slot takes the queue head and, FIFO, the split-precision
+ * requests behind it (at most 64 per batch, about 4e9 samples of work beyond the first,
+ * arena within the HBM budget) and runs them as one replay of the slot's captured graph
+ * of fused kernels (poses, geometry per signature class, ray sum per matrix tile shape,
+ * partial-sum reduction), each one launch over the work items of every request in the
+ * batch, its grid set to the batch's item count.  Binary64 requests, and ray sums off the matrix-core path, run alone on a
+ * slot.  Each request's H is bitwise the one drt_cfr gives for it.  req->H is borrowed
+ * until drt_poll reports done or an error. */
 int drt_submit(drt_ctx *ctx, const drt_request *req, uint64_t *ticket);
 
 /* Non-blocking status of a ticket; a ticket reported done or failed is forgotten
  * afterwards (DRT_E_NOTFOUND on the next poll). */
 int drt_poll(drt_ctx *ctx, uint64_t ticket, drt_req_stat *stat);
+
+/* Serving counters since the context was created. */
+typedef struct {
+  int64_t batches;            /* graph replays of the fused batch kernels */
+  int64_t batched_requests;   /* requests served inside those batches */
+  int64_t single_launches;    /* requests served alone on a slot */
+  int32_t max_batch;          /* largest batch so far */
+  int32_t slots;              /* batches that can be in flight at once (0 before the first submit) */
+} drt_serving_stats;
+int drt_serving_stats_get(drt_ctx *ctx, drt_serving_stats *out);
 
 /* Seconds on the clock used by drt_req_stat. */
 double drt_now(void);

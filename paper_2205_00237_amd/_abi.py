@@ -26,7 +26,7 @@ DRT_FP64, DRT_SPLIT, DRT_NAIVE32 = 0, 1, 2
 
 EXPORTS = ("drt_create", "drt_destroy", "drt_load_scene", "drt_unload_scene", "drt_extrapolate",
            "drt_cfr", "drt_submit", "drt_poll", "drt_now", "drt_strerror", "drt_last_error",
-           "drt_profile_enable", "drt_profile_read")
+           "drt_profile_enable", "drt_profile_read", "drt_serving_stats_get")
 PROBE_EXPORTS = ("drt_probe_mfma_f32_16x16x4", "drt_probe_mfma_f16_16x16x32", "drt_probe_sincos_rev")
 KERNELS = ("pose", "geom", "cfr", "reduce")
 
@@ -82,6 +82,11 @@ class ReqStat(C.Structure):
                 ("t_done", C.c_double)]
 
 
+class ServingStats(C.Structure):
+    _fields_ = [("batches", C.c_int64), ("batched_requests", C.c_int64), ("single_launches", C.c_int64),
+                ("max_batch", C.c_int32), ("slots", C.c_int32)]
+
+
 class Profile(C.Structure):
     _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
 
@@ -110,6 +115,7 @@ def _load():
                               C.c_int32, vp, vp]),
         "drt_submit": (C.c_int, [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]),
         "drt_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(ReqStat)]),
+        "drt_serving_stats_get": (C.c_int, [vp, C.POINTER(ServingStats)]),
         "drt_now": (C.c_double, []),
         "drt_strerror": (C.c_char_p, [C.c_int]),
         "drt_last_error": (C.c_char_p, []),
@@ -239,6 +245,12 @@ def drt_poll(ctx, ticket):
     st = ReqStat()
     _check(LIB.drt_poll(ctx, int(ticket), C.byref(st)), "drt_poll")
     return st.state, st.t_arrive, st.t_admit, st.t_done
+
+
+def drt_serving_stats_get(ctx):
+    st = ServingStats()
+    _check(LIB.drt_serving_stats_get(ctx, C.byref(st)), "drt_serving_stats_get")
+    return {k: getattr(st, k) for k, _ in ServingStats._fields_}
 
 
 def drt_now():

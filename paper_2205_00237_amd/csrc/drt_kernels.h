@@ -46,6 +46,56 @@ struct RayClasses {
   int count[CLS_COUNT];
 };
 
+// ---------------------------------------------------------------------------------------
+// Batched serving.  A batch is up to kMaxBatch split-precision requests whose ray sum runs
+// on the binary16 matrix cores.  Each kernel kind is one fused launch over the work items of
+// every request in the batch (items of request j are [off[kind][j], off[kind][j+1])): pose
+// entries, geometry waves per signature class, ray-sum tiles per MFMA tile shape, and
+// partial-sum elements.  The launches take only the device-resident descriptor, so a graph
+// captured once per slot replays for every batch with just the grid sizes updated.
+constexpr int kMaxBatch = 64;
+enum BatchKind {
+  BK_POSE = 0,
+  BK_GEOM = 1,                  // + signature class (CLS_R, CLS_D, CLS_S)
+  BK_CFR = BK_GEOM + CLS_COUNT, // + tile shape index of the ray sum
+  BK_REDUCE = BK_CFR + 5,
+  BK_COUNT
+};
+// tile shape index of (MT, NT) in the binary16 ray sum, -1 if none
+inline int cfr_shape(int MT, int NT) {
+  if (NT == 1) return MT == 1 ? 0 : -1;
+  if (NT == 2) return MT == 1 ? 1 : -1;
+  if (NT == 4) return MT == 1 ? 2 : (MT == 2 ? 3 : (MT == 4 ? 4 : -1));
+  return -1;
+}
+
+struct BatchReq {
+  SceneView sc;
+  RayClasses rc;
+  int T, n_rays, nchunk, pad;
+  double dt, f_c;
+  AnchorParams ap;
+  CfrArgs a;
+  void* pose;      // binary64 pose table [n_bodies][T]
+  void* rec;       // ray-sum records [T][n_rays]
+  float* part;     // ray-group partial sums [G][T][K] complex (G > 1)
+  float* H;        // caller's H [T][K] complex64
+};
+
+struct BatchDesc {
+  int n_req, pad;
+  long long off[BK_COUNT][kMaxBatch + 1];
+  BatchReq req[kMaxBatch];   // only the first n_req are copied to the device
+};
+
+// work items of one request per kernel kind
+void batch_items(const BatchReq& q, long long items[BK_COUNT]);
+// workgroups (of 256) a kernel kind needs for `items` work items (1 when empty)
+long long batch_grid(int kind, long long items);
+// the kernel function of a kind (to recognise graph nodes)
+void* batch_kernel(int kind);
+hipError_t launch_batch(int kind, const BatchDesc* d, int grid, hipStream_t st);
+
 size_t pose_bytes(int nb, int T, int prec);
 size_t record_bytes(int n_rays, int T, int prec);
 CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_waves, int prec, int split_path);

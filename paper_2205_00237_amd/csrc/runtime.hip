@@ -7,6 +7,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -80,11 +81,22 @@ struct Scratch {
 
 struct Request;
 
+// One batch in flight: its stream, the instantiated graph of fused batch kernels, the batch descriptor (pinned host copy and
+// device copy; the kernels read only the device copy, so the graph replays with nothing but
+// its grid sizes updated), and the scratch arena holding every request's pose table,
+// records and partial sums.
 struct Slot_ {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node[BK_COUNT] = {};     // the kernel node of each kind
+  hipKernelNodeParams kp[BK_COUNT] = {};  // its launch parameters (grid updated per batch)
+  bool on[BK_COUNT] = {};                 // node enabled in exec
+  BatchDesc* h_desc = nullptr;
+  DevBuf d_desc;
   Scratch scratch;
-  Request* req = nullptr;
+  std::vector<Request*> reqs;
 };
 
 struct Request {
@@ -116,6 +128,7 @@ struct drt_ctx {
 
   // serving
   std::vector<Slot_> slots;
+  drt_serving_stats stats{};
   std::deque<Request*> queue;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
   uint64_t next_ticket = 1;
@@ -153,11 +166,11 @@ static void dev_free(drt_ctx* c, DevBuf& b) {
 }
 
 // grow-only scratch; the stream is synchronised first so no kernel still uses the old one
-static int ensure_scratch(drt_ctx* c, Scratch& s, size_t bytes, hipStream_t st) {
+static int ensure_scratch(drt_ctx* c, Scratch& s, size_t bytes, hipStream_t st, size_t limit = SIZE_MAX) {
   if (s.buf.bytes >= bytes) return DRT_OK;
   HIP_OK(hipStreamSynchronize(st));
   dev_free(c, s.buf);
-  return dev_alloc(c, s.buf, bytes + bytes / 4);
+  return dev_alloc(c, s.buf, std::max(bytes, std::min(bytes + bytes / 4, limit)));   // headroom to regrow less
 }
 
 // ---------------------------------------------------------------------------------------
@@ -487,12 +500,95 @@ static int check_prec(int prec) {
 
 static void serve_loop(drt_ctx* c);
 
-static int start_serving(drt_ctx* c) {
-  if (c->worker_started) return DRT_OK;
-  c->slots.resize(4);
+constexpr int kSlots = 4;
+constexpr double kBatchSamples = 4e9;   // work cap of one batch (the first request always fits)
+
+// Capture the batch kernels of one slot into a graph, one chain on the slot's stream: pose,
+// the geometry classes, the ray-sum tile shapes, the partial-sum reduction.  The node of
+// each launch is taken from the capture as it is recorded, so that its grid can be set
+// (and an empty kind switched off) per batch on the instantiated graph.
+static int capture_batch_graph(drt_ctx* c, Slot_& sl) {
+  (void)c;
+  const BatchDesc* d = (const BatchDesc*)sl.d_desc.p;
+  hipStream_t m = sl.stream;
+  HIP_OK(hipStreamBeginCapture(m, hipStreamCaptureModeThreadLocal));
+  hipError_t e1 = hipSuccess;
+  for (int kind = 0; kind < BK_COUNT && e1 == hipSuccess; ++kind) {
+    if ((e1 = launch_batch(kind, d, 1, m)) != hipSuccess) break;
+    hipStreamCaptureStatus cs;
+    const hipGraphNode_t* deps = nullptr;
+    size_t nd = 0;
+    if ((e1 = hipStreamGetCaptureInfo_v2(m, &cs, nullptr, nullptr, &deps, &nd)) != hipSuccess) break;
+    if (cs != hipStreamCaptureStatusActive || nd != 1) e1 = hipErrorStreamCaptureInvalidated;
+    else sl.node[kind] = deps[0];
+  }
+  hipError_t e2 = hipStreamEndCapture(m, &sl.graph);
+  if (e1 != hipSuccess || e2 != hipSuccess)
+    return fail(DRT_E_DEVICE, "graph capture: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  for (int k = 0; k < BK_COUNT; ++k) {
+    HIP_OK(hipGraphKernelNodeGetParams(sl.node[k], &sl.kp[k]));
+    if (sl.kp[k].func != batch_kernel(k)) return fail(DRT_E_DEVICE, "graph capture: node %d is not its kernel", k);
+  }
+  HIP_OK(hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0));
+  for (int k = 0; k < BK_COUNT; ++k) sl.on[k] = true;
+  return DRT_OK;
+}
+
+// Size every kernel node of the slot's graph to this batch: grid from the item count,
+// nodes of kinds without items switched off.
+static int set_batch_grids(Slot_& sl, const BatchDesc& h) {
+  for (int k = 0; k < BK_COUNT; ++k) {
+    const long long items = h.off[k][h.n_req];
+    const bool want = items > 0;
+    if (want) {
+      const long long g = batch_grid(k, items);
+      if (g > 0x7fffffffLL) return fail(DRT_E_INVAL, "batch kernel %d needs %lld workgroups", k, g);
+      if (sl.kp[k].gridDim.x != unsigned(g)) {
+        sl.kp[k].gridDim = dim3(unsigned(g));
+        HIP_OK(hipGraphExecKernelNodeSetParams(sl.exec, sl.node[k], &sl.kp[k]));
+      }
+    }
+    if (want != sl.on[k]) {
+      HIP_OK(hipGraphNodeSetEnabled(sl.exec, sl.node[k], want ? 1 : 0));
+      sl.on[k] = want;
+    }
+  }
+  return DRT_OK;
+}
+
+static void free_slots(drt_ctx* c) {
+  for (auto& sl : c->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    if (sl.graph) (void)hipGraphDestroy(sl.graph);
+    dev_free(c, sl.scratch.buf);
+    dev_free(c, sl.d_desc);
+    if (sl.h_desc) (void)hipHostFree(sl.h_desc);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  c->slots.clear();
+}
+
+static int init_slots(drt_ctx* c) {
+  c->slots.resize(kSlots);
   for (auto& sl : c->slots) {
     HIP_OK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    HIP_OK(hipHostMalloc((void**)&sl.h_desc, sizeof(BatchDesc), hipHostMallocDefault));
+    int st;
+    if ((st = dev_alloc(c, sl.d_desc, sizeof(BatchDesc)))) return st;
+    if ((st = capture_batch_graph(c, sl))) return st;
+  }
+  return DRT_OK;
+}
+
+static int start_serving(drt_ctx* c) {
+  if (c->worker_started) return DRT_OK;
+  int st = init_slots(c);
+  if (st != DRT_OK) {
+    free_slots(c);
+    return st;
   }
   c->worker = std::thread(serve_loop, c);
   c->worker_started = true;
@@ -500,12 +596,118 @@ static int start_serving(drt_ctx* c) {
 }
 
 static void finish(drt_ctx* c, Slot_& sl, int state) {
-  Request* q = sl.req;
-  q->state = state;
-  q->t_done = drt_now_impl();
-  q->scene->inflight--;
-  c->inflight_bytes -= q->footprint;
-  sl.req = nullptr;
+  double now = drt_now_impl();
+  for (Request* q : sl.reqs) {
+    q->state = state;
+    q->t_done = now;
+    q->scene->inflight--;
+    c->inflight_bytes -= q->footprint;
+  }
+  sl.reqs.clear();
+}
+
+// A request runs in a graph batch when its ray sum is the binary16 matrix-core one.
+static bool batchable(drt_ctx* c, const Request* q, CfrPlan* p) {
+  if (q->r.precision != DRT_SPLIT) return false;
+  *p = plan(c, *q->scene, q->r.n_rays, q->r.tg.n_steps, &q->r.fg, q->r.precision);
+  return p->a.path == CFR_MFMA16 && cfr_shape(p->a.MT, p->a.NT) >= 0;
+}
+
+// Admit the queue head and, when it is batchable, the batchable requests behind it (FIFO)
+// while the batch has room, its work stays under the cap and its arena fits in the HBM
+// budget.  Returns false when the head has to wait for memory.
+static bool launch_next(drt_ctx* c, Slot_& sl) {
+  Request* head = c->queue.front();
+  CfrPlan hp;
+  const bool batch = batchable(c, head, &hp);
+  size_t budget = c->cap > c->used.load() ? c->cap - c->used.load() : 0;
+  budget += sl.scratch.buf.bytes;   // the slot's arena is re-used
+  std::vector<std::pair<Request*, CfrPlan>> take;
+  size_t arena = 0;
+  double work = 0;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  if (!batch) {
+    if (head->footprint > budget) return false;
+    take.push_back({head, plan(c, *head->scene, head->r.n_rays, head->r.tg.n_steps, &head->r.fg, head->r.precision)});
+    arena = head->footprint;
+  } else {
+    for (size_t i = 0; i < c->queue.size() && take.size() < size_t(kMaxBatch); ++i) {
+      Request* q = c->queue[i];
+      CfrPlan p;
+      if (i == 0) p = hp;
+      else if (!batchable(c, q, &p)) break;
+      double w = double(q->r.n_rays) * q->r.tg.n_steps * q->r.fg.n_sub;
+      if (i > 0 && work + w > kBatchSamples) break;
+      if (arena + al(p.total) > budget) {
+        if (i == 0) return false;
+        break;
+      }
+      take.push_back({q, p});
+      arena += al(p.total);
+      work += w;
+    }
+  }
+  double now = drt_now_impl();
+  for (size_t i = 0; i < take.size(); ++i) {
+    Request* q = take[i].first;
+    c->queue.pop_front();
+    q->state = 1;
+    q->t_admit = now;
+    c->inflight_bytes += q->footprint;
+    sl.reqs.push_back(q);
+  }
+  int st = ensure_scratch(c, sl.scratch, arena, sl.stream, budget);
+  if (st == DRT_OK && !batch) {
+    Request* q = take[0].first;
+    st = run_cfr(nullptr, *q->scene, q->r.n_rays, &q->r.tg, &q->r.fg, q->r.precision, q->r.H, take[0].second,
+                 sl.scratch.buf.p, sl.stream);
+    c->stats.single_launches++;
+  } else if (st == DRT_OK) {
+    BatchDesc* h = sl.h_desc;
+    const int n = int(take.size());
+    h->n_req = n;
+    for (int k = 0; k < BK_COUNT; ++k) h->off[k][0] = 0;
+    char* base = (char*)sl.scratch.buf.p;
+    size_t cur = 0;
+    for (int j = 0; j < n; ++j) {
+      Request* q = take[j].first;
+      const CfrPlan& p = take[j].second;
+      BatchReq& b = h->req[j];
+      b.sc = device_view(*q->scene);
+      b.rc = classes(*q->scene, q->r.n_rays);
+      b.T = q->r.tg.n_steps;
+      b.n_rays = q->r.n_rays;
+      b.nchunk = (b.T + 63) / 64;
+      b.pad = 0;
+      b.dt = q->r.tg.dt;
+      b.f_c = q->r.fg.f_c;
+      const double inv_c = 1.0 / 299792458.0;
+      b.ap = AnchorParams{p.a.f0 * inv_c, double(p.a.B) * p.a.df * inv_c, p.a.df * inv_c};
+      b.a = p.a;
+      b.pose = base + cur + p.pose_off;
+      b.rec = base + cur + p.rec_off;
+      b.part = (float*)(base + cur + p.part_off);
+      b.H = (float*)q->r.H;
+      cur += al(p.total);
+      long long items[BK_COUNT];
+      batch_items(b, items);
+      for (int k = 0; k < BK_COUNT; ++k) h->off[k][j + 1] = h->off[k][j] + items[k];
+    }
+    const size_t bytes = offsetof(BatchDesc, req) + size_t(n) * sizeof(BatchReq);
+    st = set_batch_grids(sl, *h);
+    if (st == DRT_OK && (hipMemcpyAsync(sl.d_desc.p, h, bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
+                         hipGraphLaunch(sl.exec, sl.stream) != hipSuccess))
+      st = fail(DRT_E_DEVICE, "batch launch");
+    c->stats.batches++;
+    c->stats.batched_requests += n;
+    if (n > c->stats.max_batch) c->stats.max_batch = n;
+  }
+  if (st == DRT_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = DRT_E_DEVICE;
+  if (st != DRT_OK) {
+    (void)hipStreamSynchronize(sl.stream);
+    finish(c, sl, st);
+  }
+  return true;
 }
 
 static void serve_loop(drt_ctx* c) {
@@ -515,7 +717,7 @@ static void serve_loop(drt_ctx* c) {
     bool progress = false;
     // completions
     for (auto& sl : c->slots) {
-      if (!sl.req) continue;
+      if (sl.reqs.empty()) continue;
       hipError_t e = hipEventQuery(sl.done);
       if (e == hipSuccess) {
         finish(c, sl, 2);
@@ -525,42 +727,21 @@ static void serve_loop(drt_ctx* c) {
         progress = true;
       }
     }
-    // admissions: FIFO while a stream slot and memory are free
+    // admissions: while a slot is free, batch the queue head with what waits behind it
     while (!c->queue.empty()) {
       Slot_* free_slot = nullptr;
       for (auto& sl : c->slots)
-        if (!sl.req) {
+        if (sl.reqs.empty()) {
           free_slot = &sl;
           break;
         }
-      if (!free_slot) break;
-      Request* q = c->queue.front();
-      size_t budget = c->cap > c->used.load() ? c->cap - c->used.load() : 0;
-      size_t need = q->footprint > free_slot->scratch.buf.bytes ? q->footprint - free_slot->scratch.buf.bytes : 0;
-      if (need > budget) break;   // wait for memory
-      c->queue.pop_front();
-      q->state = 1;
-      q->t_admit = drt_now_impl();
-      free_slot->req = q;
-      c->inflight_bytes += q->footprint;
-      int st = ensure_scratch(c, free_slot->scratch, q->footprint, free_slot->stream);
-      if (st == DRT_OK) {
-        CfrPlan p = plan(c, *q->scene, q->r.n_rays, q->r.tg.n_steps, &q->r.fg, q->r.precision);
-        st = run_cfr(nullptr, *q->scene, q->r.n_rays, &q->r.tg, &q->r.fg, q->r.precision, q->r.H, p,
-                     free_slot->scratch.buf.p, free_slot->stream);
-      }
-      if (st == DRT_OK && hipEventRecord(free_slot->done, free_slot->stream) != hipSuccess) st = DRT_E_DEVICE;
-      if (st != DRT_OK) finish(c, *free_slot, st);
+      if (!free_slot || !launch_next(c, *free_slot)) break;   // no slot, or waiting for memory
       progress = true;
     }
-    if (c->stop && c->queue.empty()) {
-      bool busy = false;
-      for (auto& sl : c->slots) busy = busy || sl.req;
-      if (!busy) break;
-    }
+    bool busy = false;
+    for (auto& sl : c->slots) busy = busy || !sl.reqs.empty();
+    if (c->stop && c->queue.empty() && !busy) break;
     if (!progress) {
-      bool busy = false;
-      for (auto& sl : c->slots) busy = busy || sl.req;
       if (busy)
         c->cv.wait_for(lk, std::chrono::microseconds(20));
       else
@@ -624,14 +805,9 @@ int drt_destroy(drt_ctx* c) {
     }
     c->cv.notify_all();
     c->worker.join();
-    for (auto& sl : c->slots) {
-      (void)hipStreamSynchronize(sl.stream);
-      dev_free(c, sl.scratch.buf);
-      (void)hipEventDestroy(sl.done);
-      (void)hipStreamDestroy(sl.stream);
-    }
   }
   (void)hipSetDevice(c->device);
+  free_slots(c);
   (void)hipDeviceSynchronize();
   for (auto& kv : c->scratch) dev_free(c, kv.second.buf);
   for (auto& kv : c->scenes) free_scene(c, *kv.second);
@@ -811,6 +987,14 @@ int drt_submit(drt_ctx* c, const drt_request* r, uint64_t* ticket) {
   c->reqs[q->ticket] = std::move(q);
   lk.unlock();
   c->cv.notify_all();
+  return DRT_OK;
+}
+
+int drt_serving_stats_get(drt_ctx* c, drt_serving_stats* out) {
+  if (!c || !out) return fail(DRT_E_INVAL, "null argument");
+  std::lock_guard<std::mutex> g(c->mu);
+  *out = c->stats;
+  out->slots = int32_t(c->slots.size());
   return DRT_OK;
 }
 

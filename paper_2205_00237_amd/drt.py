@@ -82,6 +82,10 @@ class Context:
     def poll(self, ticket):
         return _abi.drt_poll(self.ctx, ticket)
 
+    def serving_stats(self):
+        """Batches replayed, requests inside them, requests run alone, largest batch, slots."""
+        return _abi.drt_serving_stats_get(self.ctx)
+
     def profile(self, on=True):
         _abi.drt_profile_enable(self.ctx, on)
 

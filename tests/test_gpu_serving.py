@@ -43,31 +43,84 @@ def _wait(ctx, tickets, timeout=60.0):
 
 
 def test_alone_equals_in_mix(ctx):
+    """Split requests of every ray-sum tile shape run in graph batches, binary64 and wide-band
+    (K > 2048) requests alone on a slot; three bursts replay the batch graphs repeatedly, with
+    eager calls between them, and every result equals the request's own drt_cfr bitwise."""
     say("serving alone vs mix")
     s1, _, _ = scenes.config2(seed=11)
     s2, _, _ = scenes.config1()
     sid1, sid2 = ctx.load_scene(s1), ctx.load_scene(s2)
     rng = np.random.default_rng(0)
     reqs = []
-    for i in range(12):
+    for i in range(16):
         sid, R = (sid1, int(rng.integers(50, 5000))) if i % 3 else (sid2, 25)
         T = int(rng.integers(10, 300))
-        K = int((64, 256, 1024, 2048)[rng.integers(4)])
-        reqs.append((sid, R, scenes.TimeGrid(1e-3, T), scenes.FreqGrid(float((28e9, 60e9)[i % 2]), 400e6, K)))
+        K = int((64, 128, 256, 512, 1024, 2048)[rng.integers(6)])
+        prec = 1
+        if i in (5, 11):
+            prec = 0                    # binary64: served alone
+        if i == 7:
+            K = 4096                    # ray sum off the matrix cores: served alone
+        reqs.append((sid, R, scenes.TimeGrid(1e-3, T), scenes.FreqGrid(float((28e9, 60e9)[i % 2]), 400e6, K),
+                     prec))
     alone = []
-    for sid, R, tg, fg in reqs:
-        alone.append(ctx.cfr(sid, tg, fg, 1, n_rays=R).clone())
+    for sid, R, tg, fg, prec in reqs:
+        alone.append(ctx.cfr(sid, tg, fg, prec, n_rays=R).clone())
     torch.cuda.synchronize()
-    outs = [torch.zeros_like(a) for a in alone]
-    tickets = [ctx.submit(sid, R, tg, fg, H) for (sid, R, tg, fg), H in zip(reqs, outs)]
-    done = _wait(ctx, tickets)
-    for t, a, o in zip(tickets, alone, outs):
-        st, t_arr, t_adm, t_done = done[t]
-        assert st == 2
-        assert t_arr <= t_adm <= t_done
-        assert torch.equal(a.view(torch.float32), o.view(torch.float32))
+    before = ctx.serving_stats()
+    n_split = sum(1 for r in reqs if r[4] == 1 and r[3].n_sub <= 2048)
+    for burst in range(3):
+        outs = [torch.zeros_like(a) for a in alone]
+        tickets = [ctx.submit(sid, R, tg, fg, H, precision=prec) for (sid, R, tg, fg, prec), H in zip(reqs, outs)]
+        done = _wait(ctx, tickets)
+        for i, (t, a, o) in enumerate(zip(tickets, alone, outs)):
+            st, t_arr, t_adm, t_done = done[t]
+            assert st == 2
+            assert t_arr <= t_adm <= t_done
+            same = torch.equal(a.view(torch.int32), o.view(torch.int32))
+            if not same:
+                d = (a - o).abs()
+                say(f"  burst {burst} request {i} prec {reqs[i][4]} R {reqs[i][1]} T {reqs[i][2].n_steps} "
+                    f"K {reqs[i][3].n_sub}: max |diff| {d.max().item():.3g} at {int(d.argmax())}, "
+                    f"|H| max {a.abs().max().item():.3g}, nan alone {int(a.isnan().sum())} served {int(o.isnan().sum())}, "
+                    f"zeros served {int((o == 0).sum())}")
+            assert same, f"burst {burst} request {i}"
+        # eager work between graph replays
+        x = ctx.cfr(sid2, reqs[0][2], reqs[0][3], 1, n_rays=25)
+        assert torch.equal(x.view(torch.float32), alone[0].view(torch.float32))
+    st = ctx.serving_stats()
+    say(f"  serving stats {st}")
+    assert st["batched_requests"] - before["batched_requests"] == 3 * n_split
+    assert st["single_launches"] - before["single_launches"] == 3 * (len(reqs) - n_split)
+    assert st["batches"] > before["batches"] and st["slots"] == 4
     ctx.unload_scene(sid1)
     ctx.unload_scene(sid2)
+
+
+def test_batch_of_many(ctx):
+    """Small requests queued behind large ones are packed into batches."""
+    say("serving: packing")
+    s, tg, fg = scenes.config1()
+    sid = ctx.load_scene(s)
+    big_s, big_tg, big_fg = scenes.config2(seed=12)
+    bid = ctx.load_scene(big_s)
+    ref = ctx.cfr(sid, tg, fg, 1).clone()
+    torch.cuda.synchronize()
+    before = ctx.serving_stats()
+    Hb = torch.empty((big_tg.n_steps, big_fg.n_sub), dtype=torch.complex64, device="cuda")
+    # occupy the slots and the queue head for a few milliseconds
+    tickets = [ctx.submit(bid, len(big_s["ray_nint"]), big_tg, big_fg, Hb) for _ in range(12)]
+    outs = [torch.zeros_like(ref) for _ in range(100)]
+    tickets += [ctx.submit(sid, 25, tg, fg, H) for H in outs]
+    _wait(ctx, tickets)
+    for o in outs:
+        assert torch.equal(o.view(torch.float32), ref.view(torch.float32))
+    st = ctx.serving_stats()
+    say(f"  serving stats {st}")
+    assert st["max_batch"] >= 8
+    assert st["batched_requests"] - before["batched_requests"] == 112
+    ctx.unload_scene(sid)
+    ctx.unload_scene(bid)
 
 
 def test_admission_and_errors(ctx):

@@ -36,6 +36,50 @@ DRT_HD float mfabs(float x) { return ::fabsf(x); }
 DRT_HD bool mfinite(double x) { return isfinite(x); }
 DRT_HD bool mfinite(float x) { return isfinite(x); }
 
+// Reciprocal of the field type: binary32 field coefficients take the hardware's 1-ulp
+// reciprocal (their tolerance is 1e-5 relative), binary64 the correctly rounded quotient.
+template <class F> DRT_HD F frcp(F x) { return F(1) / x; }
+template <> DRT_HD float frcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+
+// sin and cos of |x| <= 8.  Binary64: the library functions.  Binary32: x = q pi/2 + r
+// with q = rint(2x/pi) and r = x - q pi/2 formed by two FMAs against pi/2 split in a
+// binary32 head and tail (Cody-Waite), |r| <= pi/4; Taylor polynomials of sin r (through
+// r^11) and cos r (through r^12), whose truncation is below 1e-11; quadrant from q mod 4.
+// Keeps the relative accuracy of sin near 0 (r carries it) and has no large-argument path.
+DRT_HD void sincos_small(double x, double& s, double& c) {
+  s = ::sin(x);
+  c = ::cos(x);
+}
+DRT_HD void sincos_small(float x, float& s, float& c) {
+  const float q = ::rintf(x * 0.6366197466850281f);
+  float r = ::fmaf(q, -1.5707963705062866f, x);
+  r = ::fmaf(q, 4.371138828673793e-08f, r);
+  const float r2 = r * r;
+  float ps = -1.0f / 39916800.0f;
+  ps = ::fmaf(ps, r2, 1.0f / 362880.0f);
+  ps = ::fmaf(ps, r2, -1.0f / 5040.0f);
+  ps = ::fmaf(ps, r2, 1.0f / 120.0f);
+  ps = ::fmaf(ps, r2, -1.0f / 6.0f);
+  const float sr = ::fmaf(ps * r2, r, r);
+  float pc = 1.0f / 479001600.0f;
+  pc = ::fmaf(pc, r2, -1.0f / 3628800.0f);
+  pc = ::fmaf(pc, r2, 1.0f / 40320.0f);
+  pc = ::fmaf(pc, r2, -1.0f / 720.0f);
+  pc = ::fmaf(pc, r2, 1.0f / 24.0f);
+  pc = ::fmaf(pc, r2, -0.5f);
+  const float cr = ::fmaf(pc, r2, 1.0f);
+  const int k = int(q) & 3;
+  const float a = (k & 1) ? cr : sr, b = (k & 1) ? sr : cr;
+  s = (k & 2) ? -a : a;              // sin(r + k pi/2)
+  c = ((k + 1) & 2) ? -b : b;        // cos(r + k pi/2)
+}
+
 template <class F> struct V3 { F x, y, z; };
 template <class F> DRT_HD V3<F> v3(F x, F y, F z) { return V3<F>{x, y, z}; }
 template <class F> DRT_HD V3<F> ld3(const double* p) { return V3<F>{F(p[0]), F(p[1]), F(p[2])}; }
@@ -58,7 +102,7 @@ template <class F> DRT_HD Cx<F> operator*(Cx<F> a, Cx<F> b) {
 }
 template <class F> DRT_HD Cx<F> operator*(F s, Cx<F> a) { return {s * a.re, s * a.im}; }
 template <class F> DRT_HD Cx<F> cdiv(Cx<F> a, Cx<F> b) {
-  F d = F(1) / (b.re * b.re + b.im * b.im);
+  F d = frcp(b.re * b.re + b.im * b.im);
   return {(a.re * b.re + a.im * b.im) * d, (a.im * b.re - a.re * b.im) * d};
 }
 // principal square root (non-negative real part)
@@ -66,8 +110,9 @@ template <class F> DRT_HD Cx<F> csqrt(Cx<F> w) {
   F r = msqrt(w.re * w.re + w.im * w.im);
   if (r == F(0)) return {F(0), F(0)};
   F t = msqrt((r + mfabs(w.re)) * F(0.5));
-  if (w.re >= F(0)) return {t, w.im / (F(2) * t)};
-  return {mfabs(w.im) / (F(2) * t), w.im >= F(0) ? t : -t};
+  F h = frcp(F(2) * t);
+  if (w.re >= F(0)) return {t, w.im * h};
+  return {mfabs(w.im) * h, w.im >= F(0) ? t : -t};
 }
 
 template <class F> struct Consts {
@@ -238,20 +283,32 @@ template <class F> DRT_HD Cx<F> utd_transition(F X) {
   if (X < FxParams<F>::xs) {
     F x = msqrt(X);
     F term = x, sr = F(0), si = F(0);
-#pragma unroll 4
-    for (int n = 0; n < FxParams<F>::ns; ++n) {
-      F v = term / F(2 * n + 1);
+    auto add = [&](int n, F v) {
       switch (n & 3) {         // (-j)^n
         case 0: sr += v; break;
         case 1: si -= v; break;
         case 2: sr -= v; break;
         default: si += v; break;
       }
-      term = term * X / F(n + 1);
+    };
+    if constexpr (sizeof(F) == 4) {
+      // unrolled, so the divisions by 2n+1 and n+1 become products with constants
+#pragma unroll
+      for (int n = 0; n < FxParams<F>::ns; ++n) {
+        add(n, term * (F(1) / F(2 * n + 1)));
+        term = term * X * (F(1) / F(n + 1));
+      }
+    } else {
+#pragma unroll 4
+      for (int n = 0; n < FxParams<F>::ns; ++n) {
+        add(n, term / F(2 * n + 1));
+        term = term * X / F(n + 1);
+      }
     }
     const F h = F(0.62665706865775012);      // sqrt(pi/8) = sqrt(pi)/2 * cos(pi/4)
     Cx<F> tail = cx<F>(h - sr, -h - si);     // sqrt(pi)/2 e^{-j pi/4} - S
-    Cx<F> e = cx<F>(mcos(X), msin(X));
+    Cx<F> e;
+    sincos_small(X, e.im, e.re);
     return (F(2) * x) * (cx<F>(F(0), F(1)) * (e * tail));
   }
   const int depth = FxParams<F>::depth(X);
@@ -270,9 +327,9 @@ template <class F> DRT_HD Cx<F> utd_transition(F X) {
 // = 2 sin^2(eps/2), so both are evaluated from eps (formed in the geometry type F) without
 // the cancellation of the textbook form near a shadow or reflection boundary; below
 // |eps| = 1e-8 the product is replaced by its small-eps limit.
-template <class F, class G> DRT_HD Cx<G> cot_F(F beta, F sgn, F n, G kL) {
+template <class F, class G> DRT_HD Cx<G> cot_F(F beta, F sgn, F n, F inv_2pin, G kL) {
   const F pi = Consts<F>::pi;
-  F N = mrint((beta + sgn * pi) / (F(2) * pi * n));
+  F N = mrint((beta + sgn * pi) * inv_2pin);
   F epsF = pi + sgn * beta - sgn * F(2) * pi * n * N;
   G eps = G(epsF), nn = G(n);
   if (mfabs(epsF) < F(kUtdEpsD)) {
@@ -282,10 +339,11 @@ template <class F, class G> DRT_HD Cx<G> cot_F(F beta, F sgn, F n, G kL) {
     Cx<G> inner = cx<G>(msqrt(G(2) * Consts<G>::pi * kL) * sg, G(0)) - (G(2) * kL * eps) * w;
     return nn * (inner * w);
   }
-  G h = msin(eps * G(0.5));
+  G h, hc, st, ctn;
+  sincos_small(eps * G(0.5), h, hc);                 // |eps| <= n pi <= 2 pi
+  sincos_small(eps * frcp(G(2) * nn), st, ctn);      // |eps / 2n| <= pi / 2
   Cx<G> fx = utd_transition(kL * (G(2) * h * h));
-  G ct = G(1) / mtan(eps / (G(2) * nn));
-  return ct * fx;
+  return (ctn * frcp(st)) * fx;
 }
 
 // Kouyoumjian-Pathak coefficient of a perfectly conducting wedge (soft for pol 0, hard for 1);
@@ -295,11 +353,12 @@ DRT_HD Cx<G> utd_coefficient(F phi, F phi_p, G sin_b0, F n, G k, G Ld, int pol) 
   const G pi = Consts<G>::pi;
   F bm = phi - phi_p, bp = phi + phi_p;
   G kL = k * Ld;
-  Cx<G> tm = cot_F<F, G>(bm, F(1), n, kL) + cot_F<F, G>(bm, F(-1), n, kL);
-  Cx<G> tp = cot_F<F, G>(bp, F(1), n, kL) + cot_F<F, G>(bp, F(-1), n, kL);
+  const F inv = F(1) / (F(2) * Consts<F>::pi * n);   // only picks the integer N
+  Cx<G> tm = cot_F<F, G>(bm, F(1), n, inv, kL) + cot_F<F, G>(bm, F(-1), n, inv, kL);
+  Cx<G> tp = cot_F<F, G>(bp, F(1), n, inv, kL) + cot_F<F, G>(bp, F(-1), n, inv, kL);
   Cx<G> sum = pol == DRT_PAR ? tm + tp : tm - tp;
   const G r2 = G(0.70710678118654752);
-  G scale = G(1) / (G(2) * G(n) * msqrt(G(2) * pi * k) * sin_b0);
+  G scale = frcp(G(2) * G(n) * msqrt(G(2) * pi * k) * sin_b0);
   Cx<G> pre = cx<G>(-r2 * scale, r2 * scale);                // -e^{-j pi/4} * scale
   return pre * sum;
 }
@@ -368,14 +427,14 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
 #pragma unroll
   for (int i = 0; i < N; ++i) verts[i + 1] = ch.Q[i];
   verts[N + 1] = RX;
-  V3<F> kh[N + 1];
+  V3<F> kh[N + 1], dv[N + 1];
   F len[N + 1];
   F L = F(0);
 #pragma unroll
   for (int i = 0; i <= N; ++i) {
-    V3<F> d = verts[i + 1] - verts[i];
-    len[i] = norm(d);
-    kh[i] = (F(1) / len[i]) * d;
+    dv[i] = verts[i + 1] - verts[i];
+    len[i] = norm(dv[i]);
+    kh[i] = (F(1) / len[i]) * dv[i];     // (only the Doppler, angles and scattering use it)
     L += len[i];
     ch.degen = ch.degen || !(len[i] > F(0));
   }
@@ -402,7 +461,7 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
   for (int i = 0; i < N; ++i) {
     if (SCAT || i == DP) continue;
     const DPlane& pl = sc.planes[ray.prim[i]];
-    G ct = G(mfabs(dot(kh[i], sl[i].n)));
+    G ct = G(mfabs(dot(dv[i], sl[i].n))) * frcp(G(len[i]));
     gam = gam * fresnel<G>(ct, sc.mats[pl.mat], lam, ray.pol[i]);
   }
   bool ok = ch.ok;
@@ -427,8 +486,10 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
       amp = G(tl.S) * msqrt(G(tl.area) * ci / er_norm_directive<G>(tl.alpha, ci)) * lobe;
     }
     G ph = G(tl.phase0);
-    G sc_ = lam / (G(4) * pi) * amp / (G(len[0]) * G(len[1]));
-    a = cx<G>(sc_ * mcos(ph), sc_ * msin(ph));
+    G sc_ = lam / (G(4) * pi) * amp * frcp(G(len[0]) * G(len[1]));
+    G sp_, cp_;
+    sincos_small(ph, sp_, cp_);     // tile phase in [0, 2 pi)
+    a = cx<G>(sc_ * cp_, sc_ * sp_);
   } else if constexpr (DP >= 0) {
     const DEdge& ed = sc.edges[ray.prim[DP]];
     const Slot<F>& es = sl[DP];
@@ -445,13 +506,13 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
     F phi = matan2(dot(uo, es.n), dot(uo, es.t));
     if (phi_p < F(0)) phi_p += F(2) * piF;
     if (phi < F(0)) phi += F(2) * piF;
-    G Ld = G(s * sp * sb * sb / (s + sp));
+    G Ld = G(s * sp * sb * sb) * frcp(G(s + sp));
     G k = G(2) * pi / lam;
     Cx<G> D = utd_coefficient<F, G>(phi, phi_p, G(sb), F(ed.wn), k, Ld, ray.pol[DP]);
-    G scale = lam / (G(4) * pi) / G(msqrt(sp * s * (sp + s)));
+    G scale = lam / (G(4) * pi) * frcp(msqrt(G(sp * s * (sp + s))));
     a = scale * (gam * D);
   } else {
-    a = (lam / (G(4) * pi * G(L))) * gam;
+    a = (lam * frcp(G(4) * pi * G(L))) * gam;
   }
   if (!ok) {
     res.L = res.dop = F(0);

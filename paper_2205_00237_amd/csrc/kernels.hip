@@ -44,7 +44,14 @@ __global__ __launch_bounds__(256) void k_pose(const DBody* bodies, int nb, int T
 // ---------------------------------------------------------------------------------------
 
 struct RecS { double L; float gr, gi, zr, zi; };       // split: 24 B
-struct RecM { float amp, phi0, phiB, phi1; };          // split, MFMA path: 16 B (phases in cycles)
+// split, MFMA path: 32 B.  Phases in cycles, reduced modulo one in binary64: phi0 of the
+// first subcarrier (gain argument folded in), phiB per row block of B subcarriers and phi1
+// per subcarrier (both kept in binary64, since a lane multiplies them by its row / column
+// index 0..15), and p16B, p16_1 their 16-fold multiples (the step between 16-row tiles).
+struct RecM {
+  float amp, phi0, p16B, p16_1;
+  double phiB, phi1;
+};
 struct RecD { double L, gr, gi, zr, zi; };              // binary64: 40 B
 struct RecN { float L, gr, gi, zr, zi, pad; };          // naive binary32: 24 B
 
@@ -52,13 +59,16 @@ struct RecN { float L, gr, gi, zr, zi, pad; };          // naive binary32: 24 B
 template <int PREC> struct GainT { using type = float; };
 template <> struct GainT<DRT_FP64> { using type = double; };
 
-// One wave: ray order[wave / nchunk] over the 64 instants of chunk wave % nchunk.
+// One wave: ray order[i] over the 64 instants of chunk c, where wave = 4 (nchunk (i / 4) + c) + i % 4.
 template <class F, int MODE, int PREC, int CLS>
 __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* order, int count,
                                           const typename Vec2<F>::type* pose, int T, double dt, double f_c,
                                           int n_rays, int nchunk, const ExtrapOut& eo, void* rec,
                                           const AnchorParams& ap, int wave, int lane) {
-  int i = wave / nchunk, chunk = wave - (wave / nchunk) * nchunk;
+  // the 4 waves of a workgroup take 4 consecutive rays of the class at the same 64
+  // instants, so their instant-major records of one instant land side by side
+  const int blk = wave >> 2;
+  const int i = (blk / nchunk) * 4 + (wave & 3), chunk = blk - (blk / nchunk) * nchunk;
   if (i >= count) return;
   int r = __builtin_amdgcn_readfirstlane(order[i]);
   int t = chunk * 64 + lane;
@@ -117,7 +127,10 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
     p0 -= floor(p0);
     pB -= floor(pB);
     p1 -= floor(p1);
-    reinterpret_cast<RecM*>(rec)[o] = {sqrtf(gr * gr + gi * gi), float(p0), float(pB), float(p1)};
+    double q16B = 16.0 * pB, q16_1 = 16.0 * p1;
+    q16B -= floor(q16B);
+    q16_1 -= floor(q16_1);
+    reinterpret_cast<RecM*>(rec)[o] = {sqrtf(gr * gr + gi * gi), float(p0), float(q16B), float(q16_1), pB, p1};
   } else {
     size_t o = (size_t(chunk) * n_rays + r) * 64 + lane;
     if (!active) res.gain = cx<G>(G(0), G(0));
@@ -260,6 +273,13 @@ __global__ __launch_bounds__(256) void k_cfr(const void* rec, CfrArgs a, void* o
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// frac(i * step) + base for a lane's row / column index i < 16: the product and its
+// reduction in binary64, so the step's rounding is not multiplied by i; below 2 cycles, as
+// v_sin / v_cos take it.
+__device__ __forceinline__ float row_phase(int i, double step, float base) {
+  return float(__builtin_amdgcn_fract(double(i) * step)) + base;
+}
+
 // Split-precision ray sum as complex GEMMs on the matrix cores.  With k = k1 B + k2,
 // exp(-j 2 pi f_k L/c) = exp(-j 2 pi (f_0 + k1 B df) L/c) exp(-j 2 pi k2 df L/c), so for one
 // instant H[k1 B + k2] = sum_r U[k1][r] V[r][k2] with U = a exp(-j 2 pi (f_0 + k1 B df) L/c)
@@ -269,10 +289,10 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // ray1 im).  Lane l supplies A[row l%16][slot l/16] and B[slot l/16][column l%16] and owns
 // accumulator rows 4(l/16)..4(l/16)+3 of column l%16.  Rows are k1 (MT tiles of 16), columns
 // are [C_re for k2 < B | C_im for k2 < B] (NT tiles of 16, B = 8 NT).  Operands are
-// generated on the vector ALU from the record's binary64-reduced phases: the U row phase
-// phi0 + k1 phiB and the V column phase k2 phi1 (cycles, k1, k2 < 64, so below 65) are
-// formed in binary32 and fed to v_sin/v_cos, which take revolutions and reduce them modulo
-// one exactly over [-256, 256].
+// generated on the vector ALU from the record's binary64-reduced phases: with k1 = 16 mt + m
+// the U row phase is frac(m phiB) + phi0 + mt p16B and with k2 = 16 h + m the V column phase
+// frac(m phi1) + h p16_1 (cycles, below 5), the products m phiB and m phi1 taken in
+// binary64; v_sin/v_cos take revolutions and reduce them modulo one exactly.
 template <int MT, int NT>
 __global__ __launch_bounds__(256) void k_cfr_mfma(const RecM* rec, CfrArgs a, float* out) {
   constexpr int B = 8 * NT;
@@ -296,7 +316,7 @@ __global__ __launch_bounds__(256) void k_cfr_mfma(const RecM* rec, CfrArgs a, fl
   // current one is consumed pair by pair through cross-lane shuffles
   auto load = [&](int rb) {
     int r = rb + lane;
-    return r < r1 ? rt[r] : RecM{0.f, 0.f, 0.f, 0.f};
+    return r < r1 ? rt[r] : RecM{0.f, 0.f, 0.f, 0.f, 0.0, 0.0};
   };
   RecM cur = load(r0);
   for (int rb = r0; rb < r1; rb += 64) {
@@ -308,24 +328,28 @@ __global__ __launch_bounds__(256) void k_cfr_mfma(const RecM* rec, CfrArgs a, fl
     RecM q;
     q.amp = __shfl(cur.amp, src);
     q.phi0 = __shfl(cur.phi0, src);
+    q.p16B = __shfl(cur.p16B, src);
+    q.p16_1 = __shfl(cur.p16_1, src);
     q.phiB = __shfl(cur.phiB, src);
     q.phi1 = __shfl(cur.phi1, src);
+    const float u0 = row_phase(m, q.phiB, q.phi0);
     float av[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      float ph = __builtin_fmaf(float(mt * 16 + m), q.phiB, q.phi0);
+      float ph = __builtin_fmaf(float(mt), q.p16B, u0);
       float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
       av[mt] = part == 0 ? q.amp * c : -(q.amp * s);                     // Re / Im of |a| e^{-j 2 pi ph}
     }
     float bv[NT];
     if constexpr (NT == 1) {
-      float ph = float(m & 7) * q.phi1;
+      float ph = row_phase(m & 7, q.phi1, 0.f);
       float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
       bv[0] = (m >> 3) == 0 ? (part == 0 ? c : s) : (part == 0 ? -s : c);
     } else {
+      const float v0 = row_phase(m, q.phi1, 0.f);
 #pragma unroll
       for (int h = 0; h < NT / 2; ++h) {
-        float ph = float(h * 16 + m) * q.phi1;
+        float ph = __builtin_fmaf(float(h), q.p16_1, v0);
         float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
         bv[h] = part == 0 ? c : s;                 // C_re columns: V_re, -V_im
         bv[h + NT / 2] = part == 0 ? -s : c;       // C_im columns: V_im, V_re
@@ -438,7 +462,7 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
 
   auto load = [&](int rb) {
     int r = rb + lane;
-    return r < r1 ? rt[r] : RecM{0.f, 0.f, 0.f, 0.f};
+    return r < r1 ? rt[r] : RecM{0.f, 0.f, 0.f, 0.f, 0.0, 0.0};
   };
   float amax = 0.f;
   for (int rb = r0 + lane; rb < r1; rb += 64) amax = fmaxf(amax, rt[rb].amp);
@@ -458,26 +482,29 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
       for (int j = 0; j < 4; ++j) {
         const int src = bk * 16 + grp * 4 + j;
         const float amp = __shfl(cur.amp, src) * kScale;
-        const float phi0 = __shfl(cur.phi0, src), phiB = __shfl(cur.phiB, src), phi1 = __shfl(cur.phi1, src);
+        const float phi0 = __shfl(cur.phi0, src), p16B = __shfl(cur.p16B, src), p16_1 = __shfl(cur.p16_1, src);
+        const double phiB = __shfl(cur.phiB, src), phi1 = __shfl(cur.phi1, src);
+        const float u0 = row_phase(m, phiB, phi0);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          float ph = __builtin_fmaf(float(mt * 16 + m), phiB, phi0);
+          float ph = __builtin_fmaf(float(mt), p16B, u0);
           float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
           Split16 w = split_pair<false>(amp * c, -(amp * s));   // U = |a| e^{-j 2 pi ph}
           ahw[mt][j] = w.hi;
           alw[mt][j] = w.lo;
         }
         if constexpr (NT == 1) {
-          float ph = float(m & 7) * phi1;
+          float ph = row_phase(m & 7, phi1, 0.f);
           float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
           // C_re column: (V_re, -V_im) = (c, s); C_im column: (V_im, V_re) = (-s, c)
           Split16 w = (m >> 3) == 0 ? split_pair<false>(c, s) : split_pair<false>(-s, c);
           bhw[0][j] = w.hi;
           blw[0][j] = w.lo;
         } else {
+          const float v0 = row_phase(m, phi1, 0.f);
 #pragma unroll
           for (int hh = 0; hh < NT / 2; ++hh) {
-            float ph = float(hh * 16 + m) * phi1;
+            float ph = __builtin_fmaf(float(hh), p16_1, v0);
             float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
             Split16 w = split_pair<true>(c, s);
             bhw[hh][j] = w.hi;
@@ -645,7 +672,7 @@ __global__ __launch_bounds__(256) void kb_reduce(const BatchDesc* bd) {
 void batch_items(const BatchReq& q, long long items[BK_COUNT]) {
   for (int k = 0; k < BK_COUNT; ++k) items[k] = 0;
   items[BK_POSE] = (long long)q.sc.n_bodies * q.T;
-  for (int c = 0; c < CLS_COUNT; ++c) items[BK_GEOM + c] = (long long)q.rc.count[c] * q.nchunk;
+  for (int c = 0; c < CLS_COUNT; ++c) items[BK_GEOM + c] = (long long)((q.rc.count[c] + 3) / 4) * 4 * q.nchunk;
   items[BK_CFR + cfr_shape(q.a.MT, q.a.NT)] = q.a.n_blocks;
   if (q.a.G > 1) items[BK_REDUCE] = (long long)q.T * q.a.K;
 }
@@ -717,7 +744,8 @@ size_t pose_bytes(int nb, int T, int prec) {
 }
 
 size_t record_bytes(int n_rays, int T, int prec) {
-  size_t per = prec == DRT_FP64 ? sizeof(RecD) : (prec == DRT_SPLIT ? sizeof(RecS) : sizeof(RecN));
+  size_t per = prec == DRT_FP64 ? sizeof(RecD)
+                                : (prec == DRT_SPLIT ? std::max(sizeof(RecS), sizeof(RecM)) : sizeof(RecN));
   return size_t((T + 63) / 64) * n_rays * 64 * per;
 }
 
@@ -729,8 +757,7 @@ static void launch_classes(const SceneView& sc, const RayClasses& rc, const void
   int nchunk = (T + 63) / 64;
   for (int c = 0; c < CLS_COUNT; ++c) {
     if (rc.count[c] == 0) continue;
-    long waves = long(rc.count[c]) * nchunk;
-    dim3 grid((waves + 3) / 4);
+    dim3 grid(unsigned(long((rc.count[c] + 3) / 4) * nchunk));   // 4 rays x 64 instants per workgroup
     if (c == CLS_R)
       hipLaunchKernelGGL((k_geom<F, MODE, PREC, CLS_R>), grid, dim3(256), 0, st, sc, rc.order[c], rc.count[c],
                          (P)pose, T, dt, f_c, n_rays, nchunk, eo, rec, ap);

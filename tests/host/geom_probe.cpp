@@ -39,6 +39,19 @@ int main() {
       DMat m{er, sg, pec, 0};
       Cx<double> v = fresnel<double>(ct, m, lam, pol);
       std::printf("%.17g %.17g\n", v.re, v.im);
+    } else if (!std::strcmp(fn, "SC32")) {   // binary32 sin / cos of a bounded argument
+      double x;
+      std::scanf("%lf", &x);
+      float s, c;
+      sincos_small(float(x), s, c);
+      std::printf("%.9g %.9g\n", s, c);
+    } else if (!std::strcmp(fn, "G32")) {
+      double ct, er, sg, lam;
+      int pec, pol;
+      std::scanf("%lf %lf %lf %lf %d %d", &ct, &er, &sg, &lam, &pec, &pol);
+      DMat m{er, sg, pec, 0};
+      Cx<float> v = fresnel<float>(float(ct), m, float(lam), pol);
+      std::printf("%.9g %.9g\n", v.re, v.im);
     } else if (!std::strcmp(fn, "ER64")) {
       int alpha;
       double ct;

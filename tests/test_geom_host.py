@@ -69,6 +69,34 @@ def test_wedge_coefficient(probe):
         assert abs(complex(*g32) - r) <= 3e-6 * abs(r) + 3e-7 * pre * terms, (a, g32, r)
 
 
+def test_bounded_sincos32(probe):
+    """The binary32 sin / cos of the field code against the binary64 library on |x| <= 8:
+    absolute error near rounding, and relative accuracy of sin kept near zero."""
+    x = np.concatenate([np.linspace(-8, 8, 4001), [0.0, 1e-30, -1e-20, 1e-8, 3e-5, -2e-3],
+                        np.pi / 2 * np.arange(-5, 6)]).astype(np.float32)
+    got = np.array(probe([f"SC32 {float(v)!r}" for v in x]))
+    xd = x.astype(np.float64)
+    assert np.abs(got[:, 0] - np.sin(xd)).max() < 4e-7
+    assert np.abs(got[:, 1] - np.cos(xd)).max() < 4e-7
+    small = np.abs(xd) < 0.5
+    nz = small & (xd != 0)
+    assert (np.abs(got[nz, 0] / np.sin(xd[nz]) - 1) < 3e-7).all()
+    assert (got[xd == 0, 0] == 0).all()
+
+
+def test_fresnel32(probe):
+    """Binary32 Fresnel coefficients (fast reciprocals) against the oracle."""
+    rng = np.random.default_rng(3)
+    lines, refs = [], []
+    for _ in range(300):
+        ct, er, sg, lam = rng.uniform(0, 1), rng.uniform(1, 20), rng.uniform(0, 2), rng.uniform(0.001, 0.1)
+        pec, pol = int(rng.random() < 0.2), int(rng.integers(2))
+        lines.append("G32 " + " ".join(repr(float(v)) for v in (ct, er, sg, lam)) + f" {pec} {pol}")
+        refs.append(complex(em.fresnel_gamma(ct, er, sg, lam, bool(pec), pol)))
+    for g, r in zip(probe(lines), refs):
+        assert abs(complex(*g) - r) <= 2e-6, (g, r)
+
+
 def test_fresnel_and_er_norm(probe):
     rng = np.random.default_rng(1)
     lines, refs = [], []

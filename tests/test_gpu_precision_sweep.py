@@ -1,0 +1,94 @@
+"""Precision sweep on the urban scene generator (seed 4): Tx-Rx distance 10-500 m, carriers
+6-140 GHz, 400 MHz over 1024 subcarriers, 5000 rays over 1000 instants of 0.5 ms, in the
+three arithmetic modes of the GPU path (binary64; split: binary64 geometry and phase
+reduction with binary32 field coefficients and phasor sums; naive binary32 throughout)
+against the binary64 oracle.  Geometry (length, delay, Doppler, gain) is compared on every
+5th instant and H on every 50th, all subcarriers.  Binary64 and split must meet their
+tolerances at every point of the sweep; naive binary32 is reported, and must be the worst of
+the three where the carrier phase is largest."""
+import json
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2205_00237_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+C0 = 299_792_458.0
+DISTANCES = (10.0, 30.0, 100.0, 300.0, 500.0)
+CARRIERS = (6e9, 28e9, 60e9, 140e9)
+MODES = {0: "fp64", 1: "split", 2: "naive32"}
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_00237_amd.drt import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _errors(out, ref, cols, H, Href, f_c):
+    """Max errors of one mode against the oracle on the compared instants."""
+    v_gpu = out["valid"].cpu().numpy()[:, cols].astype(bool)
+    v = v_gpu & ref["valid"]
+    L = out["L"].cpu().numpy()[:, cols]
+    dop = out["dop"].cpu().numpy()[:, cols].astype(np.float64)
+    g = out["gain"].cpu().numpy()[:, cols].astype(np.complex128)
+    gr = ref["gain"]
+    big = v & (np.abs(gr) > 1e-3 * np.abs(gr[v]).max())
+    rms = np.sqrt(np.mean(np.abs(Href) ** 2))
+    m = np.abs(Href) >= 0.1 * rms
+    return {
+        "valid_mismatch": int((v_gpu != ref["valid"]).sum()),
+        "L_m": float(np.abs(L - ref["L"])[v].max()),
+        "tau_s": float(np.abs(L - ref["L"])[v].max() / C0),
+        "doppler_hz": float(np.abs(dop - ref["dop"])[v].max()),
+        "gain_rel": float((np.abs(np.abs(g) - np.abs(gr)) / np.abs(gr))[big].max()),
+        "gain_arg_rad": float(np.abs(np.angle(g * np.conj(gr)))[big].max()),
+        "H_all": float(np.abs(H - Href).max() / rms),
+        "H_mag": float((np.abs(np.abs(H[m]) - np.abs(Href[m])) / np.abs(Href[m])).max()),
+        "H_arg_rad": float(np.abs(np.angle(H[m] * np.conj(Href[m]))).max()),
+    }
+
+
+@pytest.mark.parametrize("f_c", CARRIERS)
+@pytest.mark.parametrize("distance", DISTANCES)
+def test_precision_sweep(ctx, distance, f_c):
+    say(f"precision sweep d={distance} m f_c={f_c / 1e9:g} GHz")
+    s, tg, fg = scenes.config4(distance, f_c)
+    sid = ctx.load_scene(s)
+    cols = np.arange(0, tg.n_steps, 5)
+    rows = np.arange(0, tg.n_steps, 50)
+    ref = oracle.extrapolate(s, cols * tg.dt, fg.f_c)
+    hsel = np.searchsorted(cols, rows)
+    Href = oracle.cfr(ref["L"][:, hsel], ref["gain"][:, hsel], oracle.freq_axis(fg.f_c, fg.bandwidth, fg.n_sub))
+    res = {"distance_m": distance, "f_c_hz": f_c}
+    for prec, name in MODES.items():
+        out = ctx.extrapolate(sid, tg, fg.f_c, prec)
+        H = ctx.cfr(sid, tg, fg, prec).cpu().numpy().astype(np.complex128)[rows]
+        res[name] = _errors(out, ref, cols, H, Href, fg.f_c)
+    ctx.unload_scene(sid)
+    say("SWEEP " + json.dumps(res))
+    for name in ("fp64", "split"):
+        e = res[name]
+        assert e["valid_mismatch"] == 0, name
+        assert e["L_m"] <= 1e-9, name
+        assert e["doppler_hz"] <= 1e-5 + 2.0 ** -23 * np.abs(ref["dop"]).max(), name
+    assert res["fp64"]["H_all"] <= 1e-6
+    assert res["split"]["H_all"] <= 1e-4 and res["split"]["H_mag"] <= 1e-4 and res["split"]["H_arg_rad"] <= 1e-3
+    assert res["split"]["gain_rel"] <= 1e-4
+    if distance == DISTANCES[-1] and f_c == CARRIERS[-1]:
+        # largest carrier phase of the sweep: naive binary32 loses the phase
+        assert res["naive32"]["H_arg_rad"] > max(res["split"]["H_arg_rad"], 1e-3)

@@ -477,13 +477,17 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
     RecM nxt = load(rb + 64);
     const int nblk = min(4, (r1 - rb + 15) >> 4);
     for (int bk = 0; bk < nblk; ++bk) {
-      u32x4 ahw[MT], alw[MT], bhw[NT], blw[NT];
+      // U operands of the 16 rays (lane: rays 4 grp .. 4 grp + 3 of the block) for every
+      // row tile; the V column phases' bases, kept for the column-tile loop below
+      u32x4 ahw[MT], alw[MT];
+      float vb[4], vs[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int src = bk * 16 + grp * 4 + j;
         const float amp = __shfl(cur.amp, src) * kScale;
-        const float phi0 = __shfl(cur.phi0, src), p16B = __shfl(cur.p16B, src), p16_1 = __shfl(cur.p16_1, src);
+        const float phi0 = __shfl(cur.phi0, src), p16B = __shfl(cur.p16B, src);
         const double phiB = __shfl(cur.phiB, src), phi1 = __shfl(cur.phi1, src);
+        vs[j] = __shfl(cur.p16_1, src);
         const float u0 = row_phase(m, phiB, phi0);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -493,46 +497,54 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
           ahw[mt][j] = w.hi;
           alw[mt][j] = w.lo;
         }
-        if constexpr (NT == 1) {
-          float ph = row_phase(m & 7, phi1, 0.f);
-          float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
-          // C_re column: (V_re, -V_im) = (c, s); C_im column: (V_im, V_re) = (-s, c)
-          Split16 w = (m >> 3) == 0 ? split_pair<false>(c, s) : split_pair<false>(-s, c);
-          bhw[0][j] = w.hi;
-          blw[0][j] = w.lo;
-        } else {
-          const float v0 = row_phase(m, phi1, 0.f);
-#pragma unroll
-          for (int hh = 0; hh < NT / 2; ++hh) {
-            float ph = __builtin_fmaf(float(hh), p16_1, v0);
-            float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
-            Split16 w = split_pair<true>(c, s);
-            bhw[hh][j] = w.hi;
-            blw[hh][j] = w.lo;
-            bhw[hh + NT / 2][j] = w.rhi;
-            blw[hh + NT / 2][j] = w.rlo;
-          }
-        }
+        vb[j] = row_phase(NT == 1 ? (m & 7) : m, phi1, 0.f);
       }
-      half8 ah[MT], al[MT], bh[NT], bl[NT];
+      half8 ah[MT], al[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         ah[mt] = __builtin_bit_cast(half8, ahw[mt]);
         al[mt] = __builtin_bit_cast(half8, alw[mt]);
       }
+      // V operands one column-tile pair at a time, each consumed right away (shorter live
+      // ranges, and the matrix instructions of one pair overlap the phasors of the next)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        bh[nt] = __builtin_bit_cast(half8, bhw[nt]);
-        bl[nt] = __builtin_bit_cast(half8, blw[nt]);
-      }
+      for (int hh = 0; hh < (NT + 1) / 2; ++hh) {
+        u32x4 h0, l0, h1, l1;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mt], bh[nt], acc[mt][nt], 0, 0, 0);
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mt], bl[nt], acc[mt][nt], 0, 0, 0);
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[mt], bh[nt], acc[mt][nt], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          float ph = __builtin_fmaf(float(hh), vs[j], vb[j]);
+          float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
+          if constexpr (NT == 1) {
+            // C_re column: (V_re, -V_im) = (c, s); C_im column: (V_im, V_re) = (-s, c)
+            Split16 w = (m >> 3) == 0 ? split_pair<false>(c, s) : split_pair<false>(-s, c);
+            h0[j] = w.hi;
+            l0[j] = w.lo;
+          } else {
+            Split16 w = split_pair<true>(c, s);
+            h0[j] = w.hi;
+            l0[j] = w.lo;
+            h1[j] = w.rhi;
+            l1[j] = w.rlo;
+          }
         }
+        const half8 bh0 = __builtin_bit_cast(half8, h0), bl0 = __builtin_bit_cast(half8, l0);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          acc[mt][hh] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mt], bh0, acc[mt][hh], 0, 0, 0);
+          acc[mt][hh] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mt], bl0, acc[mt][hh], 0, 0, 0);
+          acc[mt][hh] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[mt], bh0, acc[mt][hh], 0, 0, 0);
+        }
+        if constexpr (NT > 1) {
+          const half8 bh1 = __builtin_bit_cast(half8, h1), bl1 = __builtin_bit_cast(half8, l1);
+          constexpr int o = NT / 2;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            acc[mt][hh + o] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mt], bh1, acc[mt][hh + o], 0, 0, 0);
+            acc[mt][hh + o] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mt], bl1, acc[mt][hh + o], 0, 0, 0);
+            acc[mt][hh + o] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[mt], bh1, acc[mt][hh + o], 0, 0, 0);
+          }
+        }
+      }
     }
     cur = nxt;
   }
@@ -569,8 +581,11 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
       }
 }
 
+// Four waves per SIMD for the tile shapes up to 2 x 4 (128 registers): the matrix
+// instructions of one wave overlap the phasor arithmetic of the others.
 template <int MT, int NT>
-__global__ __launch_bounds__(256) void k_cfr_mfma16(const RecM* rec, CfrArgs a, float* out) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT * NT <= 8 ? 4 : 1)))
+void k_cfr_mfma16(const RecM* rec, CfrArgs a, float* out) {
   __shared__ floatx4 red[3][64][MT * NT];
   int bid = xcd_remap(blockIdx.x, gridDim.x);
   if (bid < a.n_blocks) cfr16_tile<MT, NT>(rec, a, out, bid, red);
@@ -647,7 +662,8 @@ __global__ __launch_bounds__(256) void kb_geom(const BatchDesc* bd) {
 }
 
 template <int MT, int NT>
-__global__ __launch_bounds__(256) void kb_cfr16(const BatchDesc* bd) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT * NT <= 8 ? 4 : 1)))
+void kb_cfr16(const BatchDesc* bd) {
   __shared__ floatx4 red[3][64][MT * NT];
   const int n = bd->n_req;
   const long long* off = bd->off[BK_CFR + (NT == 1 ? 0 : (NT == 2 ? 1 : (MT == 1 ? 2 : (MT == 2 ? 3 : 4))))];

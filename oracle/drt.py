@@ -21,6 +21,16 @@ interaction points (geometry.py), and evaluates:
 A chain is inconsistent (valid = 0, every output 0) when a reflection parameter leaves
 (0, 1), a diffraction source or receiver lies on the edge line, or a scattering tile faces
 away from a terminal.
+
+Validity monitor (the multipath lifetime T_C of Sec. II: the extrapolation holds while no
+path disappears).  A consistent chain is in bounds at an instant when, on the geometry
+displaced to that instant, every reflection point lies in its wall's facet (the
+parallelogram corner + s u + w v, 0 <= s, w <= 1, carried with the wall's body) with both
+neighbouring vertices on the front side of the wall (n . (P - Q) >= 0), and every
+diffraction point lies on its edge segment (z_lo <= (Q_D - a) . e <= z_hi).  Walls without a
+facet and edges without limits are unbounded.  `bounds_margin` is the smallest of these
+signed distances in metres (facet coordinates scaled by the side lengths), `first_out` the
+first instant index at which a ray is not in bounds (the number of instants if never).
 """
 import math
 
@@ -67,6 +77,46 @@ def _moved(scene, kind, prim, poses, k_axis):
     O0 = scene["body_O0"][body][:, None, :]
     return {"body": body, "c": place_points(scene["tile_c0"][prim][:, None, :], O0, Ob, Rb),
             "n": rotate(scene["tile_n0"][prim][:, None, :], Rb)}
+
+
+def _bounds_margin(scene, kinds, prims, slots, verts, pts, poses):
+    """Smallest signed distance [m] of the chain's points to the edges of their facets /
+    segments and of the neighbouring vertices to the front side of each wall; +inf when
+    nothing bounds the chain."""
+    O, R, V, W = poses
+    Ng, T = verts[0].shape[:2]
+    margin = np.full((Ng, T), np.inf)
+    facets = scene.get("plane_facet")
+    zlim = scene.get("edge_zlim")
+    for i, kind in enumerate(kinds):
+        if kind == KIND_R:
+            nn = slots[i]["n"]
+            margin = np.minimum(margin, dot(verts[i] - pts[i], nn))        # previous vertex
+            margin = np.minimum(margin, dot(verts[i + 2] - pts[i], nn))    # next vertex
+            if facets is None:
+                continue
+            fac = facets[prims[:, i]]                                       # (Ng,3,3) corner, u, v
+            body = slots[i]["body"]
+            O0 = scene["body_O0"][body][:, None, :]
+            corner = place_points(fac[:, 0][:, None, :], O0, O[body], R[body])
+            u = rotate(fac[:, 1][:, None, :], R[body])
+            v = rotate(fac[:, 2][:, None, :], R[body])
+            d = pts[i] - corner
+            uu, uv, vv = dot(u, u), dot(u, v), dot(v, v)
+            du, dv = dot(d, u), dot(d, v)
+            bounded = (uu > 0) & (vv > 0)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                det = uu * vv - uv * uv
+                cs = (vv * du - uv * dv) / det          # d = cs u + cw v (in the wall plane)
+                cw = (uu * dv - uv * du) / det
+            lu, lv = np.sqrt(uu), np.sqrt(vv)
+            m = np.minimum(np.minimum(cs, 1.0 - cs) * lu, np.minimum(cw, 1.0 - cw) * lv)
+            margin = np.where(bounded, np.minimum(margin, m), margin)
+        elif kind == KIND_D and zlim is not None:
+            z = dot(pts[i] - slots[i]["a"], slots[i]["e"])
+            lim = zlim[prims[:, i]]
+            margin = np.minimum(margin, np.minimum(z - lim[:, 0:1], lim[:, 1:2] - z))
+    return margin
 
 
 def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
@@ -182,12 +232,16 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
         D = utd_coefficient(phi, phi_p, sin_b0, wn, k, Ld, pols[:, d][:, None])
         a = gam * lam / (4.0 * math.pi) * D / np.sqrt(sp * s * (sp + s))
 
+    margin = _bounds_margin(scene, kinds, prims, slots, verts, pts, poses)
+
     out = {"L": L, "dop": dop, "aod_az": aod_az, "aod_el": aod_el, "aoa_az": aoa_az,
            "aoa_el": aoa_el, "gain": a, "valid": valid}
     for key in out:
         if key == "valid":
             continue
         out[key] = np.where(valid, out[key], 0)
+    out["bounds_margin"] = margin
+    out["in_bounds"] = valid & (margin >= 0.0)
     out["degenerate"] = degen
     out["_pts"] = pts
     out["_khat"] = khat
@@ -197,7 +251,8 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
 def extrapolate(scene, dt, f_c, rays=None, chunk=256, keep_points=False):
     """Per-(ray, time) outputs at the time offsets dt (T,) for the rays `rays`
     (default all): dict of (R,T) arrays L [m], tau [s], dop [Hz], aod_az, aod_el, aoa_az,
-    aoa_el [rad], gain (complex), valid (bool).  With keep_points=True, also "points":
+    aoa_el [rad], gain (complex), valid (bool), in_bounds (bool), bounds_margin [m], and
+    first_out (R,) of the validity monitor.  With keep_points=True, also "points":
     list per ray of the (T,3) interaction points and "khat": the unit segment directions."""
     dt = np.atleast_1d(np.asarray(dt, dtype=np.float64))
     if rays is None:
@@ -211,6 +266,8 @@ def extrapolate(scene, dt, f_c, rays=None, chunk=256, keep_points=False):
     out["gain"] = np.zeros((R, T), dtype=np.complex128)
     out["valid"] = np.zeros((R, T), dtype=bool)
     out["degenerate"] = np.zeros((R, T), dtype=bool)
+    out["in_bounds"] = np.zeros((R, T), dtype=bool)
+    out["bounds_margin"] = np.zeros((R, T))
     if keep_points:
         out["points"] = [None] * R
         out["khat"] = [None] * R
@@ -232,6 +289,8 @@ def extrapolate(scene, dt, f_c, rays=None, chunk=256, keep_points=False):
                     out["points"][p] = [q[j] for q in g["_pts"]]
                     out["khat"][p] = [q[j] for q in g["_khat"]]
     out["tau"] = out["L"] / C0
+    ib = out["in_bounds"]
+    out["first_out"] = np.where(ib.all(axis=1), T, np.argmin(ib, axis=1)).astype(np.int64)
     return out
 
 

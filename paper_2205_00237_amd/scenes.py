@@ -25,6 +25,11 @@ Scene dictionary (all float arrays are float64, vectors are unit where stated):
     tile_body tile_alpha tile_model    (nt,) int32 / int32 / uint8 (0 Lambertian, 1 directive)
     tile_c0 tile_n0                    (nt,3) centroid and outward unit normal at t0
     tile_area tile_S tile_phase0       (nt,) area dS [m^2], scattering coefficient S, phase [rad]
+    plane_facet (optional)             (np,3,3) the wall's facet at t0: corner, u, v (the
+                                       parallelogram corner + s u + w v, 0 <= s, w <= 1);
+                                       zero u and v: unbounded wall
+    edge_zlim (optional)               (ne,2) the edge segment z_lo <= (X - a0) . e0 <= z_hi;
+                                       (-inf, inf): unbounded edge
     ray_nint                           (nr,) uint8, 0..4 interactions (0 = line of sight)
     ray_kind ray_pol ray_prim          (nr,4) uint8 kind (1 R, 2 D, 3 S) / uint8 polarisation
                                        (0 perpendicular = soft, 1 parallel = hard) / int32 primitive
@@ -96,13 +101,17 @@ class SceneBuilder:
         self.mats.append((float(eps_r), float(sigma), int(bool(pec))))
         return len(self.mats) - 1
 
-    def add_plane(self, body, mat, p0, n0):
-        self.planes.append((body, mat, np.asarray(p0, float), _unit(n0)))
+    def add_plane(self, body, mat, p0, n0, facet=None):
+        """facet: optional (corner, u, v) of the wall's parallelogram at t0."""
+        f = np.zeros((3, 3)) if facet is None else np.array([np.asarray(x, float) for x in facet])
+        self.planes.append((body, mat, np.asarray(p0, float), _unit(n0), f))
         return len(self.planes) - 1
 
-    def add_edge(self, body, a0, e0, t0, n0, wedge_n):
+    def add_edge(self, body, a0, e0, t0, n0, wedge_n, zlim=None):
+        """zlim: optional (z_lo, z_hi) of the edge segment along e0 from a0."""
+        z = (-np.inf, np.inf) if zlim is None else (float(zlim[0]), float(zlim[1]))
         self.edges.append((body, np.asarray(a0, float), _unit(e0), _unit(t0), _unit(n0),
-                           float(wedge_n)))
+                           float(wedge_n), z))
         return len(self.edges) - 1
 
     def add_tile(self, body, c0, n0, area, S, alpha, model, phase0):
@@ -138,6 +147,8 @@ class SceneBuilder:
         s["plane_mat"] = np.array([p[1] for p in P], np.int32)
         s["plane_p0"] = np.array([p[2] for p in P], f8).reshape(-1, 3)
         s["plane_n0"] = np.array([p[3] for p in P], f8).reshape(-1, 3)
+        if any(np.any(p[4] != 0) for p in P):
+            s["plane_facet"] = np.array([p[4] for p in P], f8).reshape(-1, 3, 3)
         E = self.edges
         s["edge_body"] = np.array([e[0] for e in E], np.int32)
         s["edge_a0"] = np.array([e[1] for e in E], f8).reshape(-1, 3)
@@ -145,6 +156,8 @@ class SceneBuilder:
         s["edge_t0"] = np.array([e[3] for e in E], f8).reshape(-1, 3)
         s["edge_n0"] = np.array([e[4] for e in E], f8).reshape(-1, 3)
         s["edge_wedge_n"] = np.array([e[5] for e in E], f8)
+        if any(np.isfinite(e[6][0]) or np.isfinite(e[6][1]) for e in E):
+            s["edge_zlim"] = np.array([e[6] for e in E], f8).reshape(-1, 2)
         T = self.tiles
         s["tile_body"] = np.array([t[0] for t in T], np.int32)
         s["tile_c0"] = np.array([t[1] for t in T], f8).reshape(-1, 3)
@@ -179,7 +192,8 @@ def box_frame(heading):
 
 
 def add_box(b: SceneBuilder, body, mat, centre, dims, axes=None, heading=0.0):
-    """Six face planes (outward normals) and four edges parallel to the local z axis.
+    """Six face planes (outward normals, each with its rectangular facet) and four edges
+    parallel to the local z axis (segments of the box height).
 
     Returns {"faces": {name: plane}, "edges": [edge...], "face_geom": {name: (centre,
     normal, u, v, half_u, half_v)}} where u, v span the face.  Each edge's 0-face is the
@@ -193,13 +207,13 @@ def add_box(b: SceneBuilder, body, mat, centre, dims, axes=None, heading=0.0):
             ("+y", ey, hy, ex, hx, ez, hz), ("-y", -ey, hy, ex, hx, ez, hz),
             ("+z", ez, hz, ex, hx, ey, hy), ("-z", -ez, hz, ex, hx, ey, hy)):
         c = centre + h * n
-        faces[name] = b.add_plane(body, mat, c, n)
+        faces[name] = b.add_plane(body, mat, c, n, facet=(c - hu * u - hv * v, 2 * hu * u, 2 * hv * v))
         geom[name] = (c, n, u, v, hu, hv)
     edges = []
     for sx in (1.0, -1.0):
         for sy in (1.0, -1.0):
             a0 = centre + sx * hx * ex + sy * hy * ey
-            edges.append(b.add_edge(body, a0, ez, -sy * ey, sx * ex, 1.5))
+            edges.append(b.add_edge(body, a0, ez, -sy * ey, sx * ex, 1.5, zlim=(-hz, hz)))
     return {"faces": faces, "edges": edges, "face_geom": geom}
 
 
@@ -294,10 +308,11 @@ def config2(seed=2, scale=1, separation=None, bearing=None, n_facades=200, n_box
         n = axis if np.dot(mid - c, axis) >= 0 else -axis
         along = np.array([-n[1], n[0], 0.0])
         mat = b.add_material(rng.uniform(3, 9), 0.0, False)
-        facade_planes.append(b.add_plane(0, mat, c, n))
+        up = np.array([0.0, 0.0, 1.0])
+        facade_planes.append(b.add_plane(0, mat, c, n, facet=(c - 0.5 * w * along - 0.5 * h * up, w * along, h * up)))
         for sgn in (1.0, -1.0):
             a0 = c + sgn * 0.5 * w * along
-            facade_edges.append(b.add_edge(0, a0, (0, 0, 1), -sgn * along, n, 1.5))
+            facade_edges.append(b.add_edge(0, a0, (0, 0, 1), -sgn * along, n, 1.5, zlim=(-0.5 * h, 0.5 * h)))
 
     box_planes, box_edges = [], []
     for _ in range(n_boxes):
@@ -341,7 +356,7 @@ def config2(seed=2, scale=1, separation=None, bearing=None, n_facades=200, n_box
     def edge_in_plane(e, p):
         # a reflection on a wall that contains the ray's diffracting edge makes two
         # interaction points coincide
-        _, a0, e0, _, _, _ = b.edges[e]
+        a0, e0 = b.edges[e][1], b.edges[e][2]
         p0, n0 = b.planes[p][2], b.planes[p][3]
         return abs(np.dot(e0, n0)) < 1e-12 and abs(np.dot(a0 - p0, n0)) < 1e-9
 

@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 PEAK_FP32_VECTOR = 157.3e12      # MI355X published dense vector fp32 [flop/s]
 PEAK_FP64_VECTOR = 78.6e12
 PEAK_FP16_MFMA = 2.5e15          # dense binary16 matrix cores
+PEAK_HBM = 8e12                  # HBM3E [B/s]
 PEAK_FP32_MFMA = 157.3e12        # dense binary32 matrix cores
 FLOP_PER_SAMPLE = 8              # one complex rotation (6) + one complex accumulate (2)
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2205_00237_amd", "csrc", "kernels.hip")
@@ -184,6 +185,24 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    # drt_extrapolate alone (every per-(ray, instant) output and the validity monitor), the
+    # HBM-write-bound call: 8 + 4 + 16 + 8 + 1 + 1 = 38 B per (ray, instant) and 4 B per ray
+    ext = ctx.extrapolate(sid, tg, fg.f_c, DRT_SPLIT)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    sec_ext = timed_steps(lambda: ctx.extrapolate(sid, tg, fg.f_c, DRT_SPLIT, out=ext), args.steps, 2, torch)
+    prof_ext = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    ext_bytes = R * T * 38 + R * 4
+    ext_kernel_ms = (prof_ext["pose"][0] + prof_ext["geom"][0]) / max(1, prof_ext["pose"][1])
+    extrap = {"ms_per_call": sec_ext * 1e3, "ray_instants_per_s": R * T / sec_ext,
+              "bytes_written": ext_bytes, "write_GB_per_s": ext_bytes / sec_ext / 1e9,
+              "hbm_frac": ext_bytes / sec_ext / PEAK_HBM, "kernel_ms": ext_kernel_ms,
+              "outputs": "L f64, f_D, 4 angles f32, gain c64, valid, in_bounds u8 per (ray, instant); "
+                         "first_out i32 per ray"}
+    log(f"extrapolate: {extrap}")
+    del ext
     sec64 = None
     if not args.no_fp64:
         H64 = torch.empty((T, K), dtype=torch.complex128, device="cuda")
@@ -231,6 +250,7 @@ def main():
                       "split_speedup": sec64 / sec} if sec64 else None),
         "roofline": roof,
         "step_vs_direct_sum_roofline": path_roof,
+        "extrapolate": extrap,
         "kernels": kernels,
         "scene_load_s": load_s,
     }

@@ -94,6 +94,13 @@ typedef struct {
   const uint8_t *ray_kind, *ray_pol;           /* [nr][4] drt_kind, drt_pol per interaction */
   const int32_t *ray_prim;                     /* [nr][4] index into planes / edges / tiles */
   const double *ray_q0;                        /* optional [nr][4][3] t0 interaction points; NULL = skip */
+  /* Bounds of the validity monitor (multipath lifetime, Sec. II); both optional. */
+  const double *plane_facet;                   /* [np][3][3] the wall's facet at t0: corner, u, v, the
+                                                  parallelogram corner + s u + w v, 0 <= s, w <= 1,
+                                                  u and v in the plane; u = v = 0: unbounded wall;
+                                                  NULL: every wall unbounded */
+  const double *edge_zlim;                     /* [ne][2] the edge segment z_lo <= (X - a0) . e0 <= z_hi
+                                                  (infinities allowed); NULL: every edge unbounded */
 } drt_scene_desc;
 
 /* t_j = t0 + j*dt, j = 0..n_steps-1. */
@@ -113,6 +120,12 @@ typedef struct {
   float *aod_az, *aod_el, *aoa_az, *aoa_el;    /* departure / arrival azimuth, elevation [rad] */
   void *gain;                                  /* field coefficient at f_c (no propagation phase) */
   uint8_t *valid;
+  /* Validity monitor: in_bounds = valid and, on the geometry displaced to the instant, every
+   * reflection point inside its wall's facet with both neighbouring vertices on the front
+   * side (n . (P - Q) >= 0) and every diffraction point on its edge segment; first_out
+   * ([n_rays]) = the first instant index with in_bounds = 0, n_steps if none. */
+  uint8_t *in_bounds;
+  int32_t *first_out;
 } drt_ray_out;
 
 typedef struct {

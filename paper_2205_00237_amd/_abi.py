@@ -56,6 +56,7 @@ class SceneDesc(C.Structure):
         ("n_rays", C.c_int32),
         ("ray_nint", _u8p), ("ray_kind", _u8p), ("ray_pol", _u8p), ("ray_prim", _i32p),
         ("ray_q0", _dp),
+        ("plane_facet", _dp), ("edge_zlim", _dp),
     ]
 
 
@@ -69,7 +70,8 @@ class FreqGrid(C.Structure):
 
 class RayOut(C.Structure):
     _fields_ = [("L", C.c_void_p), ("dop", C.c_void_p), ("aod_az", C.c_void_p), ("aod_el", C.c_void_p),
-                ("aoa_az", C.c_void_p), ("aoa_el", C.c_void_p), ("gain", C.c_void_p), ("valid", C.c_void_p)]
+                ("aoa_az", C.c_void_p), ("aoa_el", C.c_void_p), ("gain", C.c_void_p), ("valid", C.c_void_p),
+                ("in_bounds", C.c_void_p), ("first_out", C.c_void_p)]
 
 
 class Request(C.Structure):
@@ -192,6 +194,14 @@ def scene_desc(scene, ray_q0=None):
         q = _arr(ray_q0, np.float64, (d.n_rays, 4, 3))
         keep["ray_q0"] = q
         d.ray_q0 = q.ctypes.data_as(_dp)
+    if "plane_facet" in scene and d.n_planes:
+        f = _arr(scene["plane_facet"], np.float64, (d.n_planes, 3, 3))
+        keep["plane_facet"] = f
+        d.plane_facet = f.ctypes.data_as(_dp)
+    if "edge_zlim" in scene and d.n_edges:
+        z = _arr(scene["edge_zlim"], np.float64, (d.n_edges, 2))
+        keep["edge_zlim"] = z
+        d.edge_zlim = z.ctypes.data_as(_dp)
     return d, keep
 
 
@@ -219,7 +229,8 @@ def drt_unload_scene(ctx, sid):
 
 
 def drt_extrapolate(ctx, sid, n_rays, dt, n_steps, f_c, precision, out_ptrs, stream=0):
-    """out_ptrs: dict with any of L, dop, aod_az, aod_el, aoa_az, aoa_el, gain, valid -> device pointer."""
+    """out_ptrs: dict with any of L, dop, aod_az, aod_el, aoa_az, aoa_el, gain, valid, in_bounds,
+    first_out -> device pointer."""
     tg = TimeGrid(float(dt), int(n_steps))
     o = RayOut(**{k: int(v) for k, v in out_ptrs.items() if v})
     _check(LIB.drt_extrapolate(ctx, int(sid), int(n_rays), C.byref(tg), float(f_c), int(precision),

@@ -205,6 +205,7 @@ template <class F> struct ChainOut {
   V3<F> Q[DRT_MAX_INT];
   V3<F> A, B;         // unfolded image source / receiver of the diffraction
   F rhoA, rhoB;
+  F zQ;               // diffraction point along the edge from its reference point
   bool ok, degen;
 };
 
@@ -239,6 +240,7 @@ DRT_HD void solve_points(V3<F> TX, V3<F> RX, const Slot<F>* sl, ChainOut<F>& c) 
     c.B = B;
     c.rhoA = rA;
     c.rhoB = rB;
+    c.zQ = zQ;
   }
 }
 
@@ -397,6 +399,7 @@ template <class F, class G = F> struct RayResult {
   G aod_az, aod_el, aoa_az, aoa_el;
   Cx<G> gain;
   bool ok, degen;
+  bool in_bounds;            // validity monitor (with MON)
   V3<F> Q[DRT_MAX_INT];      // interaction points (used by the loader's t0 checks)
 };
 
@@ -409,8 +412,11 @@ template <class F> DRT_HD void dir_angles(V3<F> v, F& az, F& el) {
 // (points, length, Doppler) is computed in F; angles and the field coefficient in G.
 // Template parameters fix the signature so that every array stays in registers; the
 // interaction points are copied out only with KEEP_Q (the loader's t0 checks), since the
-// copy would otherwise survive in private memory behind the signature dispatch.
-template <class F, class G, int N, int DP, bool SCAT, bool KEEP_Q = false>
+// copy would otherwise survive in private memory behind the signature dispatch.  With MON
+// the validity monitor is evaluated too: every reflection point inside its wall's facet
+// (tested in the wall body's t0 frame, where the facet is fixed) with both neighbouring
+// vertices on the front side, and every diffraction point on its edge segment.
+template <class F, class G, int N, int DP, bool SCAT, bool KEEP_Q = false, bool MON = false>
 DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot<F>* sl, V3<F> TX,
                                 V3<F> VTX, V3<F> RX, V3<F> VRX, F f_c) {
   RayResult<F, G> res;
@@ -522,6 +528,35 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
   res.gain = a;
   res.ok = ok;
   res.degen = ch.degen;
+  res.in_bounds = ok;
+  if constexpr (MON && !SCAT) {
+    bool in = true;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (i == DP) {
+        const DEdge& ed = sc.edges[ray.prim[i]];
+        in = in && ch.zQ >= F(ed.zlo) && ch.zQ <= F(ed.zhi);
+        continue;
+      }
+      const V3<F> q = ch.Q[i], nn = sl[i].n;
+      in = in && dot(verts[i] - q, nn) >= F(0) && dot(verts[i + 2] - q, nn) >= F(0);
+      const DPlane& pl = sc.planes[ray.prim[i]];
+      if (pl.bounded) {
+        // back to the t0 frame of the wall's body: X0 = O0 + R(-theta)(X - O(t))
+        const Pose<F>& ps = sl[i].pose;
+        V3<F> x0 = q;
+        if (ps.moving) {
+          V3<F> w = q - ps.O;
+          V3<F> kw = cross(ps.k, w);
+          x0 = ps.O0 + (w - ps.s * kw + ps.c1 * cross(ps.k, kw));
+        }
+        const V3<F> d = x0 - ld3<F>(pl.c0);
+        const F su = dot(ld3<F>(pl.du), d), sv = dot(ld3<F>(pl.dv), d);
+        in = in && su >= F(0) && su <= F(1) && sv >= F(0) && sv <= F(1);
+      }
+    }
+    res.in_bounds = ok && in;
+  }
   if constexpr (KEEP_Q) {
 #pragma unroll
     for (int i = 0; i < N; ++i) res.Q[i] = ch.Q[i];

@@ -20,6 +20,8 @@ struct ExtrapOut {
   float *dop, *aod_az, *aod_el, *aoa_az, *aoa_el;
   void* gain;
   uint8_t* valid;
+  uint8_t* in_bounds;
+  int32_t* first_out;   // pre-filled with T; lowered by atomic minimum
 };
 
 // Partition of H = sum over rays: a wave owns TTc instants x (KB * kNK) subcarriers of one
@@ -106,6 +108,7 @@ hipError_t launch_geom(const SceneView& sc, const RayClasses& rc, const void* po
                        hipStream_t st);
 hipError_t launch_cfr(const void* rec, const CfrArgs& a, int prec, void* out, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st);
 hipError_t launch_reduce(const void* part, int G, size_t n, int prec, void* H, hipStream_t st);
 
 }  // namespace drt

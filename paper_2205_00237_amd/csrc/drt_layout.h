@@ -20,13 +20,18 @@ struct DMat {           // 24 B
   double eps_r, sigma;
   int32_t pec, pad;
 };
-struct DPlane {         // 56 B
+struct DPlane {         // 136 B
   double p0[3], n0[3];
+  double c0[3], du[3], dv[3];   // facet at t0: corner and the duals of its sides, so that a
+                                // point X of the plane is corner + s u + w v with
+                                // s = du . (X - c0), w = dv . (X - c0)
   int32_t body, mat;
+  int32_t bounded, pad;         // bounded = 0: the wall has no facet
 };
-struct DEdge {          // 112 B
+struct DEdge {          // 128 B
   double a0[3], e0[3], t0[3], n0[3];
   double wn;
+  double zlo, zhi;              // segment z_lo <= (X - a0) . e0 <= z_hi at t0 (may be infinite)
   int32_t body, pad;
 };
 struct DTile {          // 88 B

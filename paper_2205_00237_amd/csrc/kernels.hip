@@ -95,10 +95,15 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   F fc = F(f_c);
   using G = typename GainT<PREC>::type;
   RayResult<F, G> res = with_signature_in<F, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
-    return eval_ray<F, G, N, DP, SCAT>(sc, ray, sl, TX, VTX, RX, VRX, fc);
+    return eval_ray<F, G, N, DP, SCAT, false, MODE == GEOM_EXTRAP>(sc, ray, sl, TX, VTX, RX, VRX, fc);
   });
 
   if constexpr (MODE == GEOM_EXTRAP) {
+    if (eo.first_out) {
+      // first instant of this chunk out of bounds; the ray's minimum over chunks by atomics
+      const unsigned long long out = __ballot(active && !res.in_bounds);
+      if (out != 0ull && lane == __ffsll((long long)out) - 1) atomicMin(eo.first_out + r, t);
+    }
     if (!active) return;
     size_t o = size_t(r) * T + t;
     if (eo.L) eo.L[o] = double(res.L);
@@ -114,6 +119,7 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
         reinterpret_cast<float2*>(eo.gain)[o] = {float(res.gain.re), float(res.gain.im)};
     }
     if (eo.valid) eo.valid[o] = res.ok ? 1 : 0;
+    if (eo.in_bounds) eo.in_bounds[o] = res.in_bounds ? 1 : 0;
   } else if constexpr (MODE == GEOM_ANCHOR_MFMA) {
     // phases of the first subcarrier, of one row block and of one subcarrier, each reduced
     // modulo one cycle in binary64 before rounding to binary32; the gain enters as its
@@ -608,6 +614,11 @@ __global__ __launch_bounds__(256) void k_reduce(const C* part, int G, size_t n, 
   if (i < n) reduce_item<C>(part, G, n, H, i);
 }
 
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t* p, size_t n, int32_t v) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 __global__ __launch_bounds__(256) void k_zero(uint32_t* p, size_t n_words) {
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n_words) p[i] = 0u;
@@ -736,6 +747,12 @@ hipError_t launch_batch(int kind, const BatchDesc* d, int grid, hipStream_t st) 
 
 // ---------------------------------------------------------------------------------------
 // host-side launchers
+
+hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
   size_t n = bytes / 4;

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstddef>
@@ -246,6 +247,7 @@ static int validate_and_pack(const drt_scene_desc* d, Scene& s) {
   planes.resize(d->n_planes);
   for (int i = 0; i < d->n_planes; ++i) {
     DPlane& P = planes[i];
+    std::memset(&P, 0, sizeof P);
     std::memcpy(P.p0, d->plane_p0 + 3 * i, 24);
     std::memcpy(P.n0, d->plane_n0 + 3 * i, 24);
     P.body = d->plane_body[i];
@@ -253,6 +255,27 @@ static int validate_and_pack(const drt_scene_desc* d, Scene& s) {
     if (P.body < 0 || P.body >= d->n_bodies || P.mat < 0 || P.mat >= d->n_mat)
       return fail(DRT_E_INVAL, "plane %d: body or material index out of range", i);
     if (!unit(P.n0)) return fail(DRT_E_INVAL, "plane %d: normal is not a unit vector", i);
+    if (d->plane_facet) {
+      const double* f = d->plane_facet + 9 * i;   // corner, u, v
+      const double *c = f, *u = f + 3, *v = f + 6;
+      auto dt3 = [](const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+      const double uu = dt3(u, u), uv = dt3(u, v), vv = dt3(v, v);
+      if (uu == 0 && vv == 0) continue;   // unbounded wall
+      const double det = uu * vv - uv * uv;
+      if (!(det > 1e-12 * uu * vv) || !std::isfinite(det))
+        return fail(DRT_E_INVAL, "plane %d: facet sides are degenerate or parallel", i);
+      if (std::fabs(dt3(u, P.n0)) > 1e-9 * std::sqrt(uu) || std::fabs(dt3(v, P.n0)) > 1e-9 * std::sqrt(vv))
+        return fail(DRT_E_INVAL, "plane %d: facet sides are not in the plane", i);
+      double cp[3] = {c[0] - P.p0[0], c[1] - P.p0[1], c[2] - P.p0[2]};
+      if (std::fabs(dt3(cp, P.n0)) > 1e-9 * (1.0 + std::sqrt(dt3(cp, cp))))
+        return fail(DRT_E_INVAL, "plane %d: facet corner is not in the plane", i);
+      for (int k = 0; k < 3; ++k) {
+        P.c0[k] = c[k];
+        P.du[k] = (vv * u[k] - uv * v[k]) / det;
+        P.dv[k] = (uu * v[k] - uv * u[k]) / det;
+      }
+      P.bounded = 1;
+    }
   }
   std::vector<DEdge>& edges = s.edges;
   edges.resize(d->n_edges);
@@ -269,6 +292,13 @@ static int validate_and_pack(const drt_scene_desc* d, Scene& s) {
     if (!unit(E.e0) || !unit(E.t0) || !unit(E.n0))
       return fail(DRT_E_INVAL, "edge %d: direction, tangent or normal is not a unit vector", i);
     if (!(E.wn > 0.5 && E.wn <= 2.0)) return fail(DRT_E_INVAL, "edge %d: wedge index n must be in (0.5, 2]", i);
+    E.zlo = -INFINITY;
+    E.zhi = INFINITY;
+    if (d->edge_zlim) {
+      E.zlo = d->edge_zlim[2 * i];
+      E.zhi = d->edge_zlim[2 * i + 1];
+      if (!(E.zlo <= E.zhi)) return fail(DRT_E_INVAL, "edge %d: segment limits need z_lo <= z_hi", i);
+    }
   }
   std::vector<DTile>& tiles = s.tiles;
   tiles.resize(d->n_tiles);
@@ -881,15 +911,18 @@ int drt_extrapolate(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_g
   if (!(f_c > 0)) return fail(DRT_E_INVAL, "carrier must be > 0");
   if ((st = set_device(c))) return st;
   int T = tg->n_steps;
-  if (T == 0 || n_rays == 0) return DRT_OK;
   hipStream_t hs = (hipStream_t)stream;
+  if (n_rays == 0) return DRT_OK;
+  if (out->first_out) HIP_OK(launch_fill_i32(out->first_out, size_t(n_rays), T, hs));   // lowered by the kernels
+  if (T == 0) return DRT_OK;
   std::lock_guard<std::mutex> g(c->scratch_mu);
   Scratch& sc = c->scratch[hs];
   if ((st = ensure_scratch(c, sc, pose_bytes(s->view.n_bodies, T, prec), hs))) return st;
   HIP_OK(timed(c, DRT_K_POSE, hs, [&] {
     return launch_pose((const DBody*)s->d_bodies.p, s->view.n_bodies, T, tg->dt, prec, sc.buf.p, hs);
   }));
-  ExtrapOut eo{out->L, out->dop, out->aod_az, out->aod_el, out->aoa_az, out->aoa_el, out->gain, out->valid};
+  ExtrapOut eo{out->L,      out->dop,  out->aod_az,    out->aod_el,   out->aoa_az,
+               out->aoa_el, out->gain, out->valid, out->in_bounds, out->first_out};
   const RayClasses rc = classes(*s, n_rays);
   HIP_OK(timed(c, DRT_K_GEOM, hs, [&] {
     return launch_geom(device_view(*s), rc, sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_EXTRAP,

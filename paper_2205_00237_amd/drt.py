@@ -46,12 +46,17 @@ class Context:
         _abi.drt_unload_scene(self.ctx, sid)
         self.n_rays.pop(sid, None)
 
-    def extrapolate(self, sid, tgrid, f_c, precision=DRT_SPLIT, n_rays=None, stream=None):
-        """Per-(ray, instant) outputs as device tensors [n_rays][n_steps]."""
+    def extrapolate(self, sid, tgrid, f_c, precision=DRT_SPLIT, n_rays=None, stream=None, out=None):
+        """Per-(ray, instant) outputs as device tensors [n_rays][n_steps] (first_out: [n_rays]);
+        `out` may pass a dict of preallocated tensors (any subset) to write instead."""
         R = self.n_rays[sid] if n_rays is None else int(n_rays)
         T = int(tgrid.n_steps)
         dev = self.device
         gdt = torch.complex128 if precision == DRT_FP64 else torch.complex64
+        if out is not None:
+            _abi.drt_extrapolate(self.ctx, sid, R, tgrid.dt, T, f_c, precision,
+                                 {k: v.data_ptr() for k, v in out.items()}, _stream(stream))
+            return out
         out = {"L": torch.empty((R, T), dtype=torch.float64, device=dev),
                "dop": torch.empty((R, T), dtype=torch.float32, device=dev),
                "aod_az": torch.empty((R, T), dtype=torch.float32, device=dev),
@@ -59,7 +64,9 @@ class Context:
                "aoa_az": torch.empty((R, T), dtype=torch.float32, device=dev),
                "aoa_el": torch.empty((R, T), dtype=torch.float32, device=dev),
                "gain": torch.empty((R, T), dtype=gdt, device=dev),
-               "valid": torch.empty((R, T), dtype=torch.uint8, device=dev)}
+               "valid": torch.empty((R, T), dtype=torch.uint8, device=dev),
+               "in_bounds": torch.empty((R, T), dtype=torch.uint8, device=dev),
+               "first_out": torch.empty((R,), dtype=torch.int32, device=dev)}
         _abi.drt_extrapolate(self.ctx, sid, R, tgrid.dt, T, f_c, precision,
                              {k: v.data_ptr() for k, v in out.items()}, _stream(stream))
         return out

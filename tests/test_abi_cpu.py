@@ -54,11 +54,31 @@ def test_missing_library_fails_loudly(monkeypatch):
         _abi._load()
 
 
-def test_struct_layouts_match_the_header():
-    """ctypes mirrors of the C structs: sizes fixed by the header's member lists (x86-64 ABI)."""
+def test_struct_layouts_match_the_header(tmp_path):
+    """ctypes mirrors of the C structs: size and every member offset equal to what a C
+    compiler makes of include/drt.h."""
+    import shutil
+    import subprocess
     from paper_2205_00237_amd import _abi
-    assert ctypes.sizeof(_abi.TimeGrid) == 16
-    assert ctypes.sizeof(_abi.FreqGrid) == 24
-    assert ctypes.sizeof(_abi.RayOut) == 64
-    assert ctypes.sizeof(_abi.Request) == 4 + 4 + 16 + 24 + 4 + 4 + 8
-    assert ctypes.sizeof(_abi.ReqStat) == 32
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    pairs = [("drt_scene_desc", _abi.SceneDesc), ("drt_time_grid", _abi.TimeGrid),
+             ("drt_freq_grid", _abi.FreqGrid), ("drt_ray_out", _abi.RayOut),
+             ("drt_request", _abi.Request), ("drt_req_stat", _abi.ReqStat),
+             ("drt_profile", _abi.Profile), ("drt_serving_stats", _abi.ServingStats)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "drt.h"', "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{cname}.{f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for cname, cls in pairs:
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert int(got[f"{cname}.{f[0]}"]) == getattr(cls, f[0]).offset, (cname, f[0])

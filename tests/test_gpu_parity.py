@@ -46,10 +46,23 @@ def h_errors(H, Href):
     return e_all, e_mag, e_arg
 
 
+def check_monitor(out, ref, where):
+    """Validity monitor: bitwise equal to the oracle except where the oracle's margin puts an
+    interaction point within 1e-9 m of a facet, segment or front-side boundary."""
+    ib = out["in_bounds"].cpu().numpy().astype(bool)
+    near = np.abs(ref["bounds_margin"]) < 1e-9
+    bad = (ib != ref["in_bounds"]) & ~near
+    assert not bad.any(), f"{where}: in_bounds differs at {np.argwhere(bad)[:5]}"
+    fo = out["first_out"].cpu().numpy()
+    sure = ~near.any(axis=1)
+    assert np.array_equal(fo[sure], ref["first_out"][sure]), f"{where}: first_out differs"
+
+
 def check_extrapolation(out, ref, prec, where, f_c):
     from paper_2205_00237_amd.drt import DRT_FP64
     v = out["valid"].cpu().numpy().astype(bool)
     assert np.array_equal(v, ref["valid"]), f"{where}: valid flags differ at {np.argwhere(v != ref['valid'])[:5]}"
+    check_monitor(out, ref, where)
     L = out["L"].cpu().numpy()
     assert np.abs(L - ref["L"]).max() <= 1e-9, f"{where}: |dL| {np.abs(L - ref['L']).max()}"
     dop = out["dop"].cpu().numpy().astype(np.float64)

@@ -203,6 +203,26 @@ def main():
                          "first_out i32 per ray"}
     log(f"extrapolate: {extrap}")
     del ext
+    # kinematics of the interaction points (second-order jets): positions, velocities,
+    # accelerations (3 x 96 B) and the Doppler rate (4 B) per (ray, instant)
+    kin = {k: torch.empty((R, T, 4, 3), dtype=torch.float64, device="cuda") for k in ("q_pos", "q_vel", "q_acc")}
+    kin["dop_rate"] = torch.empty((R, T), dtype=torch.float32, device="cuda")
+    kin["valid"] = torch.empty((R, T), dtype=torch.uint8, device="cuda")
+    sec_kin = timed_steps(lambda: ctx.extrapolate(sid, tg, fg.f_c, DRT_SPLIT, out=kin), max(3, args.steps // 4), 1, torch)
+    # second-order Taylor extrapolation of the points from t0 against the re-solved points
+    ok = kin["valid"].bool().all(dim=1)
+    q0, v0, a0 = (kin[k][:, 0] for k in ("q_pos", "q_vel", "q_acc"))
+    taylor = {}
+    for j in (20, 100, 200):
+        d = j * tg.dt
+        err = torch.linalg.vector_norm(q0 + v0 * d + 0.5 * a0 * d * d - kin["q_pos"][:, j], dim=-1).amax(dim=-1)
+        taylor[f"{d * 1e3:g} ms"] = float(err[ok].max()) if bool(ok.any()) else None
+    kin_bytes = R * T * (3 * 96 + 4 + 1)
+    kinematics = {"ms_per_call": sec_kin * 1e3, "ray_instants_per_s": R * T / sec_kin,
+                  "bytes_written": kin_bytes, "write_GB_per_s": kin_bytes / sec_kin / 1e9,
+                  "taylor_point_error_m": taylor, "rays_valid_throughout": int(ok.sum())}
+    log(f"kinematics: {kinematics}")
+    del kin
     sec64 = None
     if not args.no_fp64:
         H64 = torch.empty((T, K), dtype=torch.complex128, device="cuda")
@@ -251,6 +271,7 @@ def main():
         "roofline": roof,
         "step_vs_direct_sum_roofline": path_roof,
         "extrapolate": extrap,
+        "kinematics": kinematics,
         "kernels": kernels,
         "scene_load_s": load_s,
     }

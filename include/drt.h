@@ -126,6 +126,15 @@ typedef struct {
    * ([n_rays]) = the first instant index with in_bounds = 0, n_steps if none. */
   uint8_t *in_bounds;
   int32_t *first_out;
+  /* Kinematics of the interaction points (Sec. III-A.1 eqs. ref_point_velo and ref_point_acc,
+   * App. B and C), each [n_rays][n_steps][4][3] binary64, interaction slots beyond the ray's
+   * count zero: positions, velocities [m/s] and accelerations [m/s^2], exact time derivatives
+   * of the re-solved points (computed as second-order jets in binary64 for every precision);
+   * dop_rate ([n_rays][n_steps]) = -(f_c/c) d^2 L/dt^2 [Hz/s].  Written where the chain is
+   * consistent (reflection parameters in (0, 1), diffraction source and receiver off the
+   * edge line; scattering always), zero elsewhere. */
+  double *q_pos, *q_vel, *q_acc;
+  float *dop_rate;
 } drt_ray_out;
 
 typedef struct {

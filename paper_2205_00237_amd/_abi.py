@@ -71,7 +71,8 @@ class FreqGrid(C.Structure):
 class RayOut(C.Structure):
     _fields_ = [("L", C.c_void_p), ("dop", C.c_void_p), ("aod_az", C.c_void_p), ("aod_el", C.c_void_p),
                 ("aoa_az", C.c_void_p), ("aoa_el", C.c_void_p), ("gain", C.c_void_p), ("valid", C.c_void_p),
-                ("in_bounds", C.c_void_p), ("first_out", C.c_void_p)]
+                ("in_bounds", C.c_void_p), ("first_out", C.c_void_p),
+                ("q_pos", C.c_void_p), ("q_vel", C.c_void_p), ("q_acc", C.c_void_p), ("dop_rate", C.c_void_p)]
 
 
 class Request(C.Structure):
@@ -230,7 +231,7 @@ def drt_unload_scene(ctx, sid):
 
 def drt_extrapolate(ctx, sid, n_rays, dt, n_steps, f_c, precision, out_ptrs, stream=0):
     """out_ptrs: dict with any of L, dop, aod_az, aod_el, aoa_az, aoa_el, gain, valid, in_bounds,
-    first_out -> device pointer."""
+    first_out, q_pos, q_vel, q_acc, dop_rate -> device pointer."""
     tg = TimeGrid(float(dt), int(n_steps))
     o = RayOut(**{k: int(v) for k, v in out_ptrs.items() if v})
     _check(LIB.drt_extrapolate(ctx, int(sid), int(n_rays), C.byref(tg), float(f_c), int(precision),

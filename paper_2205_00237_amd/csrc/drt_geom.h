@@ -80,6 +80,36 @@ DRT_HD void sincos_small(float x, float& s, float& c) {
   c = ((k + 1) & 2) ? -b : b;        // cos(r + k pi/2)
 }
 
+// Second-order jet in time (value, first and second time derivative) for the velocities
+// and accelerations of the interaction points (eqs. ref_point_velo, ref_point_acc; App. B,
+// C): the geometry templates run on it unchanged and differentiate themselves by the
+// product, quotient and square-root rules; comparisons look at the value.
+template <class F> struct J2 {
+  F v, d, dd;
+  J2() = default;
+  DRT_HD J2(F x) : v(x), d(F(0)), dd(F(0)) {}
+  DRT_HD J2(F x, F x1, F x2) : v(x), d(x1), dd(x2) {}
+  friend DRT_HD J2 operator+(J2 a, J2 b) { return {a.v + b.v, a.d + b.d, a.dd + b.dd}; }
+  friend DRT_HD J2 operator-(J2 a, J2 b) { return {a.v - b.v, a.d - b.d, a.dd - b.dd}; }
+  friend DRT_HD J2 operator-(J2 a) { return {-a.v, -a.d, -a.dd}; }
+  friend DRT_HD J2 operator*(J2 a, J2 b) {
+    return {a.v * b.v, a.d * b.v + a.v * b.d, a.dd * b.v + F(2) * a.d * b.d + a.v * b.dd};
+  }
+  friend DRT_HD J2 operator/(J2 a, J2 b) {
+    const F q = a.v / b.v, q1 = (a.d - q * b.d) / b.v;
+    return {q, q1, (a.dd - F(2) * q1 * b.d - q * b.dd) / b.v};
+  }
+  friend DRT_HD bool operator<(J2 a, J2 b) { return a.v < b.v; }
+  friend DRT_HD bool operator>(J2 a, J2 b) { return a.v > b.v; }
+  friend DRT_HD bool operator<=(J2 a, J2 b) { return a.v <= b.v; }
+  friend DRT_HD bool operator>=(J2 a, J2 b) { return a.v >= b.v; }
+};
+template <class F> DRT_HD J2<F> msqrt(J2<F> a) {
+  const F r = msqrt(a.v), r1 = a.d / (F(2) * r);
+  return {r, r1, (a.dd - F(2) * r1 * r1) / (F(2) * r)};
+}
+template <class F> DRT_HD bool mfinite(J2<F> a) { return mfinite(a.v) && mfinite(a.d) && mfinite(a.dd); }
+
 template <class F> struct V3 { F x, y, z; };
 template <class F> DRT_HD V3<F> v3(F x, F y, F z) { return V3<F>{x, y, z}; }
 template <class F> DRT_HD V3<F> ld3(const double* p) { return V3<F>{F(p[0]), F(p[1]), F(p[2])}; }
@@ -561,6 +591,40 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
 #pragma unroll
     for (int i = 0; i < N; ++i) res.Q[i] = ch.Q[i];
   }
+  return res;
+}
+
+// Interaction points and path length of one ray with its slots moved as jets in time:
+// values, velocities and accelerations of the points, L, dL/dt and d2L/dt2.  ok as the
+// chain's consistency in eval_ray (reflection parameters in (0, 1), diffraction source and
+// receiver off the edge line); a scattering point is always consistent here.
+template <class J> struct KinResult {
+  V3<J> Q[DRT_MAX_INT];
+  J L;
+  bool ok;
+};
+template <class J, int N, int DP, bool SCAT>
+DRT_HD KinResult<J> kin_ray(const Slot<J>* sl, V3<J> TX, V3<J> RX) {
+  KinResult<J> res;
+  ChainOut<J> ch;
+  if constexpr (SCAT) {
+    ch.ok = true;
+    ch.degen = false;
+    ch.Q[0] = sl[0].p;
+  } else {
+    solve_points<J, N, DP>(TX, RX, sl, ch);
+  }
+  V3<J> prev = TX;
+  J L = J(0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    L = L + norm(ch.Q[i] - prev);
+    prev = ch.Q[i];
+    res.Q[i] = ch.Q[i];
+  }
+  L = L + norm(RX - prev);
+  res.L = L;
+  res.ok = ch.ok && !ch.degen && mfinite(L);
   return res;
 }
 

@@ -9,7 +9,7 @@
 
 namespace drt {
 
-enum GeomMode { GEOM_EXTRAP = 0, GEOM_ANCHOR = 1, GEOM_ANCHOR_MFMA = 2 };
+enum GeomMode { GEOM_EXTRAP = 0, GEOM_ANCHOR = 1, GEOM_ANCHOR_MFMA = 2, GEOM_KIN = 3 };
 enum CfrPath { CFR_VALU = 0, CFR_MFMA = 1, CFR_MFMA16 = 2 };
 
 constexpr int kNK = 16;          // subcarriers walked by one lane from its phase anchor
@@ -22,6 +22,8 @@ struct ExtrapOut {
   uint8_t* valid;
   uint8_t* in_bounds;
   int32_t* first_out;   // pre-filled with T; lowered by atomic minimum
+  double *q_pos, *q_vel, *q_acc;   // [R][T][4][3] interaction points and their time derivatives
+  float* dop_rate;                 // [R][T] Doppler rate at f_c [Hz/s]
 };
 
 // Partition of H = sum over rays: a wave owns TTc instants x (KB * kNK) subcarriers of one

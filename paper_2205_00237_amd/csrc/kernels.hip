@@ -75,6 +75,59 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   bool active = t < T;
   int tq = active ? t : T - 1;
   const DRay& ray = sc.rays[r];
+  if constexpr (MODE == GEOM_KIN) {
+    // the chain as jets in time (binary64): points, velocities, accelerations, L'' (Sec.
+    // III-A.1 eqs. ref_point_velo, ref_point_acc; App. B, C); the body angle's jet from the
+    // pose table's sin(theta), 1 - cos(theta) and theta' = w0 + wdot t, theta'' = wdot
+    using J = J2<double>;
+    const double tt = double(tq) * dt;
+    const J tj(tt, 1.0, 0.0);
+    const J hj = J(0.5) * tj * tj;
+    const V3<J> TXj = ld3<J>(sc.tx_p) + tj * ld3<J>(sc.tx_v) + hj * ld3<J>(sc.tx_a);
+    const V3<J> RXj = ld3<J>(sc.rx_p) + tj * ld3<J>(sc.rx_v) + hj * ld3<J>(sc.rx_a);
+    Slot<J> sj[DRT_MAX_INT];
+    const int nint = ray.nint;
+#pragma unroll
+    for (int i = 0; i < DRT_MAX_INT; ++i) {
+      if (i < nint) {
+        const int b = ray.body[i];
+        const DBody& B = sc.bodies[b];
+        const auto pe = pose[b * T + tq];
+        const double sn = double(pe.x), c1 = double(pe.y), cs = 1.0 - c1;
+        const double w1 = B.w0 + B.wdot * tt, w2 = B.wdot;
+        const J sth(sn, cs * w1, -sn * w1 * w1 + cs * w2), cth(c1, sn * w1, cs * w1 * w1 + sn * w2);
+        load_slot<J>(sc, ray.kind[i], ray.prim[i], make_pose<J>(B, tj, sth, cth), sj[i]);
+      }
+    }
+    KinResult<J> kr = with_signature_in<J, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
+      return kin_ray<J, N, DP, SCAT>(sj, TXj, RXj);
+    });
+    if (!active) return;
+    const size_t o = size_t(r) * T + t;
+    if (eo.dop_rate) eo.dop_rate[o] = kr.ok ? float(-(f_c / 299792458.0) * kr.L.dd) : 0.f;
+#pragma unroll
+    for (int i = 0; i < DRT_MAX_INT; ++i) {
+      const bool w = kr.ok && i < nint;
+      const V3<J> q = kr.Q[i];
+      const size_t e = (o * DRT_MAX_INT + i) * 3;
+      if (eo.q_pos) {
+        eo.q_pos[e] = w ? q.x.v : 0.0;
+        eo.q_pos[e + 1] = w ? q.y.v : 0.0;
+        eo.q_pos[e + 2] = w ? q.z.v : 0.0;
+      }
+      if (eo.q_vel) {
+        eo.q_vel[e] = w ? q.x.d : 0.0;
+        eo.q_vel[e + 1] = w ? q.y.d : 0.0;
+        eo.q_vel[e + 2] = w ? q.z.d : 0.0;
+      }
+      if (eo.q_acc) {
+        eo.q_acc[e] = w ? q.x.dd : 0.0;
+        eo.q_acc[e + 1] = w ? q.y.dd : 0.0;
+        eo.q_acc[e + 2] = w ? q.z.dd : 0.0;
+      }
+    }
+    return;
+  }
   F dtj = F(double(tq) * dt);
   F half = F(0.5) * dtj * dtj;
   V3<F> TX = ld3<F>(sc.tx_p) + dtj * ld3<F>(sc.tx_v) + half * ld3<F>(sc.tx_a);
@@ -809,6 +862,9 @@ static hipError_t launch_geom_mode(const SceneView& sc, const RayClasses& rc, co
                                    const AnchorParams& ap, hipStream_t st) {
   if constexpr (MODE == GEOM_ANCHOR_MFMA) {
     launch_classes<double, MODE, DRT_SPLIT>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
+  } else if constexpr (MODE == GEOM_KIN) {
+    (void)prec;   // jets in binary64 whatever the call's precision (binary64 pose table)
+    launch_classes<double, MODE, DRT_FP64>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
   } else {
     if (prec == DRT_FP64)
       launch_classes<double, MODE, DRT_FP64>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
@@ -828,6 +884,8 @@ hipError_t launch_geom(const SceneView& sc, const RayClasses& rc, const void* po
     return launch_geom_mode<GEOM_EXTRAP>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
   if (mode == GEOM_ANCHOR_MFMA)
     return launch_geom_mode<GEOM_ANCHOR_MFMA>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
+  if (mode == GEOM_KIN)
+    return launch_geom_mode<GEOM_KIN>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
   return launch_geom_mode<GEOM_ANCHOR>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
 }
 

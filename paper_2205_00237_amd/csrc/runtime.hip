@@ -917,17 +917,44 @@ int drt_extrapolate(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_g
   if (T == 0) return DRT_OK;
   std::lock_guard<std::mutex> g(c->scratch_mu);
   Scratch& sc = c->scratch[hs];
-  if ((st = ensure_scratch(c, sc, pose_bytes(s->view.n_bodies, T, prec), hs))) return st;
-  HIP_OK(timed(c, DRT_K_POSE, hs, [&] {
-    return launch_pose((const DBody*)s->d_bodies.p, s->view.n_bodies, T, tg->dt, prec, sc.buf.p, hs);
-  }));
-  ExtrapOut eo{out->L,      out->dop,  out->aod_az,    out->aod_el,   out->aoa_az,
-               out->aoa_el, out->gain, out->valid, out->in_bounds, out->first_out};
+  const bool kin = out->q_pos || out->q_vel || out->q_acc || out->dop_rate;
+  const bool ext = out->L || out->dop || out->aod_az || out->aod_el || out->aoa_az || out->aoa_el || out->gain ||
+                   out->valid || out->in_bounds || out->first_out;
+  // the kinematics outputs are jets in binary64: they need the binary64 pose table
+  const size_t pb = pose_bytes(s->view.n_bodies, T, prec), pb64 = pose_bytes(s->view.n_bodies, T, DRT_FP64);
+  const bool extra64 = kin && prec == DRT_NAIVE32;
+  const size_t off64 = extra64 ? (pb + 255) / 256 * 256 : 0;
+  if ((st = ensure_scratch(c, sc, off64 + (extra64 ? pb64 : pb), hs))) return st;
   const RayClasses rc = classes(*s, n_rays);
-  HIP_OK(timed(c, DRT_K_GEOM, hs, [&] {
-    return launch_geom(device_view(*s), rc, sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_EXTRAP,
-                       eo, nullptr, AnchorParams{0.0, 0.0, 0.0}, hs);
-  }, class_kernels(rc, T)));
+  const DBody* bodies = (const DBody*)s->d_bodies.p;
+  if (ext) {
+    HIP_OK(timed(c, DRT_K_POSE, hs, [&] {
+      return launch_pose(bodies, s->view.n_bodies, T, tg->dt, prec, sc.buf.p, hs);
+    }));
+    ExtrapOut eo{out->L,      out->dop,  out->aod_az,    out->aod_el,   out->aoa_az,
+                 out->aoa_el, out->gain, out->valid, out->in_bounds, out->first_out,
+                 nullptr,     nullptr,   nullptr,    nullptr};
+    HIP_OK(timed(c, DRT_K_GEOM, hs, [&] {
+      return launch_geom(device_view(*s), rc, sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_EXTRAP,
+                         eo, nullptr, AnchorParams{0.0, 0.0, 0.0}, hs);
+    }, class_kernels(rc, T)));
+  }
+  if (kin) {
+    char* p64 = (char*)sc.buf.p + off64;
+    if (extra64 || !ext)
+      HIP_OK(timed(c, DRT_K_POSE, hs, [&] {
+        return launch_pose(bodies, s->view.n_bodies, T, tg->dt, DRT_FP64, p64, hs);
+      }));
+    ExtrapOut ko{};
+    ko.q_pos = out->q_pos;
+    ko.q_vel = out->q_vel;
+    ko.q_acc = out->q_acc;
+    ko.dop_rate = out->dop_rate;
+    HIP_OK(timed(c, DRT_K_GEOM, hs, [&] {
+      return launch_geom(device_view(*s), rc, p64, T, tg->dt, f_c, n_rays, prec, GEOM_KIN, ko, nullptr,
+                         AnchorParams{0.0, 0.0, 0.0}, hs);
+    }, class_kernels(rc, T)));
+  }
   return DRT_OK;
 }
 

@@ -46,8 +46,10 @@ class Context:
         _abi.drt_unload_scene(self.ctx, sid)
         self.n_rays.pop(sid, None)
 
-    def extrapolate(self, sid, tgrid, f_c, precision=DRT_SPLIT, n_rays=None, stream=None, out=None):
+    def extrapolate(self, sid, tgrid, f_c, precision=DRT_SPLIT, n_rays=None, stream=None, out=None,
+                    kinematics=False):
         """Per-(ray, instant) outputs as device tensors [n_rays][n_steps] (first_out: [n_rays]);
+        with kinematics=True also q_pos, q_vel, q_acc [n_rays][n_steps][4][3] and dop_rate.
         `out` may pass a dict of preallocated tensors (any subset) to write instead."""
         R = self.n_rays[sid] if n_rays is None else int(n_rays)
         T = int(tgrid.n_steps)
@@ -67,6 +69,10 @@ class Context:
                "valid": torch.empty((R, T), dtype=torch.uint8, device=dev),
                "in_bounds": torch.empty((R, T), dtype=torch.uint8, device=dev),
                "first_out": torch.empty((R,), dtype=torch.int32, device=dev)}
+        if kinematics:
+            for k in ("q_pos", "q_vel", "q_acc"):
+                out[k] = torch.empty((R, T, 4, 3), dtype=torch.float64, device=dev)
+            out["dop_rate"] = torch.empty((R, T), dtype=torch.float32, device=dev)
         _abi.drt_extrapolate(self.ctx, sid, R, tgrid.dt, T, f_c, precision,
                              {k: v.data_ptr() for k, v in out.items()}, _stream(stream))
         return out

@@ -28,15 +28,14 @@ def bin_index(x, lo, step, n):
     return np.where((k >= 0) & (k < n), k, -1).astype(np.int64)
 
 
-def power_profiles(scene, j, dt, f_c, bins, rays=None):
-    """Profiles over the instants t = j * dt (j: integer indices into the time grid).
+def bin_samples(ex, j, bins):
+    """Profiles of the extrapolate() outputs `ex` at the grid instants j (its columns).
 
     bins: dict with steps_per_bin, n_dop, dop_lo, dop_step, n_delay, delay_lo, delay_step
     and in_bounds_only.  Returns dict with pdfp (n_tb, n_dop), pdp (n_tb, n_delay) and
     total (n_tb,) for time bins 0 .. max(j) // steps_per_bin, and the samples behind them:
-    power, dop, tau, counted (R, len(j)) and tbin (len(j),)."""
+    power, dop, tau, counted, bounds_margin (R, len(j)) and tbin (len(j),)."""
     j = np.atleast_1d(np.asarray(j, dtype=np.int64))
-    ex = extrapolate(scene, j * dt, f_c, rays=rays)
     spb = int(bins["steps_per_bin"])
     n_tb = int(j.max()) // spb + 1
     tb = j // spb
@@ -47,21 +46,25 @@ def power_profiles(scene, j, dt, f_c, bins, rays=None):
     out = {"pdfp": np.zeros((n_tb, int(bins["n_dop"]))),
            "pdp": np.zeros((n_tb, int(bins["n_delay"]))),
            "total": np.zeros(n_tb)}
-    kd = bin_index(ex["dop"], bins["dop_lo"], bins["dop_step"], int(bins["n_dop"]))
-    kt = bin_index(ex["tau"], bins["delay_lo"], bins["delay_step"], int(bins["n_delay"]))
-    R = power.shape[0]
-    for r in range(R):
-        for c in range(len(j)):
-            if not counted[r, c]:
-                continue
-            b, p = tb[c], power[r, c]
-            out["total"][b] += p
-            if kd[r, c] >= 0:
-                out["pdfp"][b, kd[r, c]] += p
-            if kt[r, c] >= 0:
-                out["pdp"][b, kt[r, c]] += p
-    out.update(power=power, dop=ex["dop"], tau=ex["tau"], counted=counted, tbin=tb)
+    r, c = np.nonzero(counted)
+    b, p = tb[c], power[r, c]
+    np.add.at(out["total"], b, p)
+    kd = bin_index(ex["dop"][r, c], bins["dop_lo"], bins["dop_step"], int(bins["n_dop"]))
+    m = kd >= 0
+    np.add.at(out["pdfp"], (b[m], kd[m]), p[m])
+    kt = bin_index(ex["tau"][r, c], bins["delay_lo"], bins["delay_step"], int(bins["n_delay"]))
+    m = kt >= 0
+    np.add.at(out["pdp"], (b[m], kt[m]), p[m])
+    out.update(power=power, dop=ex["dop"], tau=ex["tau"], counted=counted,
+               bounds_margin=ex["bounds_margin"], tbin=tb)
     return out
+
+
+def power_profiles(scene, j, dt, f_c, bins, rays=None):
+    """Profiles over the instants t = j * dt (j: integer indices into the time grid): the
+    samples of extrapolate() binned by bin_samples()."""
+    j = np.atleast_1d(np.asarray(j, dtype=np.int64))
+    return bin_samples(extrapolate(scene, j * dt, f_c, rays=rays), j, bins)
 
 
 def edge_distance(x, lo, step):

@@ -223,6 +223,28 @@ def main():
                   "taylor_point_error_m": taylor, "rays_valid_throughout": int(ok.sum())}
     log(f"kinematics: {kinematics}")
     del kin
+    # power-Doppler and power-delay profiles (incoherent bin sums of |a|^2) over 10 ms x 100 Hz
+    # and 10 ms x 2.5 ns bins: the geometry and field work of extrapolate, binned in-kernel
+    pbins = dict(steps_per_bin=20, n_dop=512, dop_lo=-25600.0, dop_step=100.0,
+                 n_delay=2048, delay_lo=0.0, delay_step=2.5e-9, in_bounds_only=0)
+    pp = ctx.power_profiles(sid, tg, fg.f_c, pbins)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    sec_pp = timed_steps(lambda: ctx.power_profiles(sid, tg, fg.f_c, pbins, out=pp), args.steps, 2, torch)
+    prof_pp = ctx.profile_read(reset=True)
+    gated = dict(pbins, in_bounds_only=1)
+    sec_ppg = timed_steps(lambda: ctx.power_profiles(sid, tg, fg.f_c, gated, out=pp), args.steps, 2, torch)
+    ctx.profile(False)
+    counted = float(pp["total"].sum())
+    profiles = {"ms_per_call": sec_pp * 1e3, "ray_instants_per_s": R * T / sec_pp,
+                "geom_kernel_ms": prof_pp["geom"][0] / max(1, prof_pp["pose"][1]),
+                "gated_ms_per_call": sec_ppg * 1e3,
+                "bins": {"time_bins": (T + 19) // 20, "doppler": 512, "delay": 2048,
+                         "time_s": 20 * tg.dt, "doppler_hz": 100.0, "delay_s": 2.5e-9},
+                "gated_counted_power": counted}
+    log(f"power profiles: {profiles}")
+    del pp
     sec64 = None
     if not args.no_fp64:
         H64 = torch.empty((T, K), dtype=torch.complex128, device="cuda")
@@ -272,6 +294,7 @@ def main():
         "step_vs_direct_sum_roofline": path_roof,
         "extrapolate": extrap,
         "kinematics": kinematics,
+        "power_profiles": profiles,
         "kernels": kernels,
         "scene_load_s": load_s,
     }

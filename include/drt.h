@@ -179,6 +179,106 @@ int drt_unload_scene(drt_ctx *ctx, uint32_t scene_id);
 int drt_extrapolate(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_grid *tg,
                     double f_c, int32_t precision, const drt_ray_out *out, void *stream);
 
+/* Classes of paths a snapshot trace looks for. */
+typedef struct {
+  int32_t max_refl;           /* 0..3: paths of 1..max_refl reflections */
+  int32_t max_refl_diff;      /* -1..2: paths of one diffraction and 0..max_refl_diff reflections
+                                 (the edge at every position); -1: none */
+  int32_t scattering;         /* 1: single diffuse scattering from every tile */
+  int32_t los;                /* 1: the line of sight */
+} drt_trace_opts;
+
+typedef struct {
+  int32_t n_paths;            /* rays of the new scene */
+  int32_t n_los, n_refl, n_diff, n_scat;
+  int64_t candidates;         /* interaction sequences examined */
+  int64_t geometric;          /* of which the interaction points exist (before obstruction) */
+} drt_trace_info;
+
+/* Snapshot ray trace at the instant t0 + t of `scene` (Sec. II: the conventional RT whose
+ * rays DRT extrapolates, re-run at the end of each multipath lifetime T_C), by the image
+ * method on every candidate interaction sequence of the classes in *opts, in binary64:
+ * images and back-tracking for reflections (Sec. III-A.2), the unfolded closed form for the
+ * diffraction point (Sec. III-B eq. diff_point).  A sequence is a path when every reflection
+ * parameter lies in (0, 1), every reflection point lies in its wall's facet (walls without a
+ * facet are unbounded) with both neighbouring vertices more than 1e-9 m in front of the wall,
+ * the diffraction point lies on its edge segment with the directions to both neighbours in
+ * the wedge's exterior (angle from the 0-face in [0, n pi]), a tile faces both terminals,
+ * and no wall's facet (or unbounded wall) crosses any segment of the path more than 1e-7 m
+ * from both of its ends.  Creates a new resident scene (*new_scene): the primitives, bodies
+ * and terminals of `scene` carried to t0 + t (body reference points, velocities and angular
+ * speeds advanced; primitive indices unchanged) and one ray per path, ordered by class (line
+ * of sight; 1..max_refl reflections; one diffraction with 0, 1, 2 reflections, edge first to
+ * edge last; scattering) and then by primitive indices.  Polarisation flags: perpendicular
+ * for walls with |n_z| <= 0.5 and vertical edges (|e_z| > 0.5), parallel otherwise;
+ * perpendicular for tiles.  Synchronous.  Errors: DRT_E_INVAL for options out of range or a
+ * non-finite t; DRT_E_NOTFOUND; DRT_E_NOMEM. */
+int drt_trace(drt_ctx *ctx, uint32_t scene, double t, const drt_trace_opts *opts,
+              uint32_t *new_scene, drt_trace_info *info);
+
+typedef struct {
+  double threshold_db;        /* rays within this many dB of the strongest at a segment's first
+                                 instant are the major ones (>= 0) */
+  int32_t max_steps;          /* longest segment in instants (>= 1): paths that appear are only
+                                 found by the next trace */
+  int32_t min_steps;          /* shortest segment in instants, 1..max_steps */
+} drt_refresh_opts;
+
+/* Multipath lifetimes over the time grid (Sec. II: the extrapolation holds for a time T_C over
+ * which no major path disappears; at its end the conventional trace is run again).  From
+ * instant j = 0: trace `scene` at t0 + j dt (drt_trace with *topts), extrapolate the traced
+ * scene over the next m = min(max_steps, n_steps - j) instants in binary64 with the validity
+ * monitor, take as major the rays whose power |a|^2 at instant j lies within threshold_db of
+ * the strongest, and end the segment at the first instant at which a major ray is out of
+ * bounds (drt_ray_out first_out), clamped to [min_steps, m]; continue from there.  Writes,
+ * for segment k < *n_segments: its first instant seg_start[k], its length seg_len[k] and the
+ * resident scene seg_scene[k] traced at its start (the caller unloads them); the instants
+ * of segment k are 0..seg_len[k]-1 of that scene's own time grid.  Synchronous.  Errors:
+ * DRT_E_INVAL for bad options or more than max_segments segments (no scene is left
+ * resident then), and those of drt_trace. */
+int drt_segments(drt_ctx *ctx, uint32_t scene, const drt_time_grid *tg, double f_c,
+                 const drt_trace_opts *topts, const drt_refresh_opts *ropts, int32_t max_segments,
+                 int32_t *seg_start, int32_t *seg_len, uint32_t *seg_scene, int32_t *n_segments);
+
+/* Copy the interaction sequences of a resident scene's rays into caller-owned host arrays
+ * of `cap` rays ([cap] nint, [cap][4] kind, prim, pol; any may be NULL); *n_rays receives
+ * the scene's ray count (the copy stops at cap). */
+int drt_scene_rays(drt_ctx *ctx, uint32_t scene, int32_t cap, int32_t *n_rays, uint8_t *nint,
+                   uint8_t *kind, int32_t *prim, uint8_t *pol);
+
+/* Bins of the power profiles.  Instant j falls in time bin j / steps_per_bin; a Doppler
+ * shift f_D in bin floor((f_D - dop_lo) / dop_step) and a delay tau in bin
+ * floor((tau - delay_lo) / delay_step), counted only when that index lies in [0, n_dop) or
+ * [0, n_delay).  Both divisions are correctly rounded binary64. */
+typedef struct {
+  double dop_lo, dop_step;          /* Hz; dop_step > 0 */
+  double delay_lo, delay_step;      /* s; delay_step > 0 */
+  int32_t steps_per_bin;            /* instants per time bin, >= 1 */
+  int32_t n_dop, n_delay;           /* bins per time bin, >= 0 each */
+  int32_t in_bounds_only;           /* 1: count only samples the validity monitor finds in bounds */
+} drt_bins;
+
+/* Caller-owned device outputs of drt_power_profiles, binary64, n_tb = ceil(n_steps /
+ * steps_per_bin) time bins, row-major with the time bin slowest; any may be NULL. */
+typedef struct {
+  double *pdfp;                     /* [n_tb][n_dop] power-Doppler profile */
+  double *pdp;                      /* [n_tb][n_delay] power-delay profile */
+  double *total;                    /* [n_tb] power of every counted sample, in a bin or not */
+} drt_power_out;
+
+/* Power-Doppler profile (Sec. IV-A) and power-delay profile (Sec. IV-B) of rays [0, n_rays)
+ * over the time grid: each (ray, instant) sample whose chain is consistent (and in bounds,
+ * with in_bounds_only) adds its power |a|^2, a being its field coefficient at carrier f_c
+ * (unit transmitted power, isotropic antennas), incoherently to the bin of its time and
+ * Doppler shift, to the bin of its time and delay tau = L / c, and to its time bin's total.
+ * The outputs are cleared and then accumulated on `stream` with binary64 atomic additions,
+ * so the order of the additions, and the last bits of a sum, can differ between calls.
+ * Errors: DRT_E_INVAL for steps_per_bin < 1, a step that is not > 0, negative bin counts
+ * or a NULL output whose count is nonzero (total may always be NULL). */
+int drt_power_profiles(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_grid *tg,
+                       double f_c, int32_t precision, const drt_bins *bins,
+                       const drt_power_out *out, void *stream);
+
 /* Time-variant transfer function H[j][k] = sum_r a_r(t_j) exp(-j 2 pi f_k L_r(t_j) / c)
  * for rays [0, n_rays), written to the device buffer H ([n_steps][n_sub], interleaved
  * complex128 for DRT_FP64, complex64 otherwise) on `stream`.  Deterministic: the same

@@ -25,12 +25,12 @@ from .em import (fresnel_gamma, utd_transition, utd_coefficient, er_norm_directi
 from .drt import extrapolate, cfr, run, freq_axis, C0
 from .rates import rates, taylor_points
 from .profiles import power_profiles, bin_samples, bin_index
-from .tracer import trace, path_exists, moved_scene
+from .tracer import trace, path_exists, moved_scene, rebase, with_rays, segments
 
 __all__ = [
     "terminal_state", "rodrigues", "body_poses", "place_points", "rotate",
     "material_velocity", "mirror", "reflection_chain", "edge_point", "direction_angles",
     "fresnel_gamma", "utd_transition", "utd_coefficient", "er_norm_directive", "er_gain",
     "extrapolate", "cfr", "run", "freq_axis", "C0", "rates", "taylor_points",
-    "power_profiles", "bin_samples", "bin_index", "trace", "path_exists", "moved_scene",
+    "power_profiles", "bin_samples", "bin_index", "trace", "path_exists", "moved_scene", "rebase", "with_rays", "segments",
 ]

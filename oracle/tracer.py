@@ -8,8 +8,9 @@ interaction sequence; it is a path when:
 * reflections (walls w_1..w_n, consecutive walls distinct): with the images of TX through
   the walls in order and the points back-tracked from RX (geometry.reflection_chain), every
   parameter s lies in (0, 1), every point lies in its wall's facet (a parallelogram, edges
-  included; a wall without a facet is unbounded) and both neighbouring vertices lie strictly
-  on the wall's front side, n . (P - Q) > 0;
+  included; a wall without a facet is unbounded) and both neighbouring vertices lie on the
+  wall's front side by more than 1e-9 m, n . (P - Q) > 1e-9 (a wall that contains the
+  ray's diffracting edge puts the segment between them inside the wall: not a path);
 * one diffraction, with reflections before and after it: the edge point comes from the
   unfolded closed form (eq. diff_point) between the image of TX through the walls before the
   edge and the image of RX through the walls after it; it lies on the edge segment, and the
@@ -32,10 +33,12 @@ import numpy as np
 
 from .kinematics import terminal_state, body_poses, place_points, rotate
 from .geometry import dot, norm, reflection_chain, edge_point
+from .drt import extrapolate
 
 KIND_R, KIND_D, KIND_S = 1, 2, 3
 POL_PERP, POL_PAR = 0, 1
 SEG_EPS = 1e-7
+FRONT_EPS = 1e-9   # a neighbour this close to a wall's plane is grazing, not in front
 
 
 def moved_scene(scene, t):
@@ -110,7 +113,7 @@ def obstructed(ms, A, B, chunk=2048):
 
 
 def _front(ms, pl, X, Q):
-    return dot(X - Q, ms["n"][pl]) > 0.0
+    return dot(X - Q, ms["n"][pl]) > FRONT_EPS
 
 
 def _wedge_angle(ms, ed, Q, X):
@@ -230,4 +233,74 @@ def trace(scene, t=0.0, max_refl=2, max_refl_diff=1, scattering=True, los=True):
         for i in np.nonzero(ok)[0]:
             prims = tuple(int(x) for x in cand[i])
             out.append((kinds, prims, pols_of(ms, kinds, prims), float(L[i])))
+    return out
+
+
+def rebase(scene, t):
+    """The scene carried to the instant t0 + t: terminals by eq. Taylor; each body's
+    reference point, velocity and angular speed advanced; every primitive placed with its
+    body's pose at t (kinematics.py); rays unchanged."""
+    t = float(t)
+    out = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in scene.items()}
+    out["t0"] = scene.get("t0", 0.0) + t
+    for w in ("tx", "rx"):
+        p, v = terminal_state(scene[w + "_p"], scene[w + "_v"], scene[w + "_a"], np.array([t]))
+        out[w + "_p"], out[w + "_v"] = p[0], v[0]
+    O, R, V, W = body_poses(scene, np.array([t]))
+    O, R = O[:, 0], R[:, 0]
+    O0 = scene["body_O0"]
+    out["body_O0"] = O
+    out["body_v0"] = V[:, 0]
+    out["body_w0"] = W[:, 0]
+    pb, eb, tb = scene["plane_body"], scene["edge_body"], scene["tile_body"]
+    out["plane_p0"] = place_points(scene["plane_p0"], O0[pb], O[pb], R[pb])
+    out["plane_n0"] = rotate(scene["plane_n0"], R[pb])
+    if "plane_facet" in scene:
+        F = scene["plane_facet"]
+        out["plane_facet"] = np.stack([place_points(F[:, 0], O0[pb], O[pb], R[pb]),
+                                       rotate(F[:, 1], R[pb]), rotate(F[:, 2], R[pb])], axis=1)
+    out["edge_a0"] = place_points(scene["edge_a0"], O0[eb], O[eb], R[eb])
+    for k in ("edge_e0", "edge_t0", "edge_n0"):
+        out[k] = rotate(scene[k], R[eb])
+    out["tile_c0"] = place_points(scene["tile_c0"], O0[tb], O[tb], R[tb])
+    out["tile_n0"] = rotate(scene["tile_n0"], R[tb])
+    return out
+
+
+def with_rays(scene, paths):
+    """The scene with its rays replaced by the traced paths [(kinds, prims, pols, L)]."""
+    out = dict(scene)
+    n = len(paths)
+    out["ray_nint"] = np.array([len(k) for k, *_ in paths], np.uint8).reshape(n)
+    out["ray_kind"] = np.zeros((n, 4), np.uint8)
+    out["ray_prim"] = np.zeros((n, 4), np.int32)
+    out["ray_pol"] = np.zeros((n, 4), np.uint8)
+    for r, (k, p, q, _) in enumerate(paths):
+        out["ray_kind"][r, :len(k)] = k
+        out["ray_prim"][r, :len(k)] = p
+        out["ray_pol"][r, :len(k)] = q
+    return out
+
+
+def segments(scene, dt, n_steps, f_c, trace_opts, threshold_db, max_steps, min_steps=1):
+    """Multipath lifetimes (Sec. II: the extrapolation holds over T_C while no major path
+    disappears; at its end the conventional trace is run again).  From instant j (starting
+    at 0): trace at t0 + j dt, carry the scene there, extrapolate its rays over the next
+    m = min(max_steps, n_steps - j) instants with the validity monitor; the major rays are
+    those whose power at instant j is within threshold_db of the strongest; the segment
+    lasts until the first instant at which a major ray is out of bounds, at least min_steps
+    and at most m instants.  Returns [(j, length, paths)]."""
+    j, out = 0, []
+    while j < n_steps:
+        paths = trace(scene, j * dt, **trace_opts)
+        m = min(max_steps, n_steps - j)
+        length = m
+        if paths:
+            sc = with_rays(rebase(scene, j * dt), paths)
+            ex = extrapolate(sc, np.arange(m) * dt, f_c)
+            p0 = np.abs(ex["gain"][:, 0]) ** 2
+            major = p0 >= p0.max() * 10.0 ** (-threshold_db / 10.0)
+            length = int(min(m, max(min_steps, ex["first_out"][major].min())))
+        out.append((j, length, paths))
+        j += length
     return out

@@ -25,6 +25,7 @@ DRT_E_INCONSISTENT = -8
 DRT_FP64, DRT_SPLIT, DRT_NAIVE32 = 0, 1, 2
 
 EXPORTS = ("drt_create", "drt_destroy", "drt_load_scene", "drt_unload_scene", "drt_extrapolate",
+           "drt_power_profiles", "drt_trace", "drt_scene_rays", "drt_segments",
            "drt_cfr", "drt_submit", "drt_poll", "drt_now", "drt_strerror", "drt_last_error",
            "drt_profile_enable", "drt_profile_read", "drt_serving_stats_get")
 PROBE_EXPORTS = ("drt_probe_mfma_f32_16x16x4", "drt_probe_mfma_f16_16x16x32", "drt_probe_sincos_rev")
@@ -75,6 +76,30 @@ class RayOut(C.Structure):
                 ("q_pos", C.c_void_p), ("q_vel", C.c_void_p), ("q_acc", C.c_void_p), ("dop_rate", C.c_void_p)]
 
 
+class TraceOpts(C.Structure):
+    _fields_ = [("max_refl", C.c_int32), ("max_refl_diff", C.c_int32), ("scattering", C.c_int32),
+                ("los", C.c_int32)]
+
+
+class TraceInfo(C.Structure):
+    _fields_ = [("n_paths", C.c_int32), ("n_los", C.c_int32), ("n_refl", C.c_int32), ("n_diff", C.c_int32),
+                ("n_scat", C.c_int32), ("candidates", C.c_int64), ("geometric", C.c_int64)]
+
+
+class RefreshOpts(C.Structure):
+    _fields_ = [("threshold_db", C.c_double), ("max_steps", C.c_int32), ("min_steps", C.c_int32)]
+
+
+class Bins(C.Structure):
+    _fields_ = [("dop_lo", C.c_double), ("dop_step", C.c_double), ("delay_lo", C.c_double),
+                ("delay_step", C.c_double), ("steps_per_bin", C.c_int32), ("n_dop", C.c_int32),
+                ("n_delay", C.c_int32), ("in_bounds_only", C.c_int32)]
+
+
+class PowerOut(C.Structure):
+    _fields_ = [("pdfp", C.c_void_p), ("pdp", C.c_void_p), ("total", C.c_void_p)]
+
+
 class Request(C.Structure):
     _fields_ = [("scene", C.c_uint32), ("n_rays", C.c_int32), ("tg", TimeGrid), ("fg", FreqGrid),
                 ("precision", C.c_int32), ("H", C.c_void_p)]
@@ -116,6 +141,13 @@ def _load():
                                       C.c_int32, C.POINTER(RayOut), vp]),
         "drt_cfr": (C.c_int, [vp, C.c_uint32, C.c_int32, C.POINTER(TimeGrid), C.POINTER(FreqGrid),
                               C.c_int32, vp, vp]),
+        "drt_trace": (C.c_int, [vp, C.c_uint32, C.c_double, C.POINTER(TraceOpts), C.POINTER(C.c_uint32),
+                                C.POINTER(TraceInfo)]),
+        "drt_segments": (C.c_int, [vp, C.c_uint32, C.POINTER(TimeGrid), C.c_double, C.POINTER(TraceOpts),
+                                   C.POINTER(RefreshOpts), C.c_int32, vp, vp, vp, C.POINTER(C.c_int32)]),
+        "drt_scene_rays": (C.c_int, [vp, C.c_uint32, C.c_int32, C.POINTER(C.c_int32), vp, vp, vp, vp]),
+        "drt_power_profiles": (C.c_int, [vp, C.c_uint32, C.c_int32, C.POINTER(TimeGrid), C.c_double,
+                                         C.c_int32, C.POINTER(Bins), C.POINTER(PowerOut), vp]),
         "drt_submit": (C.c_int, [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]),
         "drt_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(ReqStat)]),
         "drt_serving_stats_get": (C.c_int, [vp, C.POINTER(ServingStats)]),
@@ -236,6 +268,58 @@ def drt_extrapolate(ctx, sid, n_rays, dt, n_steps, f_c, precision, out_ptrs, str
     o = RayOut(**{k: int(v) for k, v in out_ptrs.items() if v})
     _check(LIB.drt_extrapolate(ctx, int(sid), int(n_rays), C.byref(tg), float(f_c), int(precision),
                                C.byref(o), C.c_void_p(int(stream))), "drt_extrapolate")
+
+
+def drt_trace(ctx, sid, t, max_refl, max_refl_diff, scattering, los):
+    """Returns (new scene id, info dict)."""
+    o = TraceOpts(int(max_refl), int(max_refl_diff), int(bool(scattering)), int(bool(los)))
+    new, info = C.c_uint32(), TraceInfo()
+    _check(LIB.drt_trace(ctx, int(sid), float(t), C.byref(o), C.byref(new), C.byref(info)), "drt_trace")
+    return new.value, {k: getattr(info, k) for k, _ in TraceInfo._fields_}
+
+
+def drt_segments(ctx, sid, dt, n_steps, f_c, trace_opts, threshold_db, max_steps, min_steps=1,
+                 max_segments=4096):
+    """[(first instant, length, scene id)] of the multipath lifetimes."""
+    import numpy as np
+    o = TraceOpts(int(trace_opts.get("max_refl", 2)), int(trace_opts.get("max_refl_diff", 1)),
+                  int(bool(trace_opts.get("scattering", True))), int(bool(trace_opts.get("los", True))))
+    r = RefreshOpts(float(threshold_db), int(max_steps), int(min_steps))
+    start = np.zeros(max_segments, np.int32)
+    length = np.zeros(max_segments, np.int32)
+    scene = np.zeros(max_segments, np.uint32)
+    n = C.c_int32()
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    _check(LIB.drt_segments(ctx, int(sid), C.byref(TimeGrid(float(dt), int(n_steps))), float(f_c), C.byref(o),
+                            C.byref(r), int(max_segments), ptr(start), ptr(length), ptr(scene), C.byref(n)),
+           "drt_segments")
+    return [(int(start[k]), int(length[k]), int(scene[k])) for k in range(n.value)]
+
+
+def drt_scene_rays(ctx, sid):
+    """(nint [n], kind [n][4], prim [n][4], pol [n][4]) numpy arrays of a resident scene."""
+    import numpy as np
+    n = C.c_int32()
+    _check(LIB.drt_scene_rays(ctx, int(sid), 0, C.byref(n), None, None, None, None), "drt_scene_rays")
+    nint = np.zeros(n.value, np.uint8)
+    kind = np.zeros((n.value, 4), np.uint8)
+    prim = np.zeros((n.value, 4), np.int32)
+    pol = np.zeros((n.value, 4), np.uint8)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    _check(LIB.drt_scene_rays(ctx, int(sid), n.value, C.byref(n), ptr(nint), ptr(kind), ptr(prim), ptr(pol)),
+           "drt_scene_rays")
+    return nint, kind, prim, pol
+
+
+def drt_power_profiles(ctx, sid, n_rays, dt, n_steps, f_c, precision, bins, out_ptrs, stream=0):
+    """bins: dict of the drt_bins fields; out_ptrs: dict with any of pdfp, pdp, total -> device pointer."""
+    tg = TimeGrid(float(dt), int(n_steps))
+    b = Bins(float(bins["dop_lo"]), float(bins["dop_step"]), float(bins["delay_lo"]),
+             float(bins["delay_step"]), int(bins["steps_per_bin"]), int(bins["n_dop"]),
+             int(bins["n_delay"]), int(bins.get("in_bounds_only", 0)))
+    o = PowerOut(**{k: int(v) for k, v in out_ptrs.items() if v})
+    _check(LIB.drt_power_profiles(ctx, int(sid), int(n_rays), C.byref(tg), float(f_c), int(precision),
+                                  C.byref(b), C.byref(o), C.c_void_p(int(stream))), "drt_power_profiles")
 
 
 def drt_cfr(ctx, sid, n_rays, dt, n_steps, f_c, bandwidth, n_sub, precision, H_ptr, stream=0):

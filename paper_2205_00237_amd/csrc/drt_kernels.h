@@ -9,7 +9,7 @@
 
 namespace drt {
 
-enum GeomMode { GEOM_EXTRAP = 0, GEOM_ANCHOR = 1, GEOM_ANCHOR_MFMA = 2, GEOM_KIN = 3 };
+enum GeomMode { GEOM_EXTRAP = 0, GEOM_ANCHOR = 1, GEOM_ANCHOR_MFMA = 2, GEOM_KIN = 3, GEOM_POWER = 4 };
 enum CfrPath { CFR_VALU = 0, CFR_MFMA = 1, CFR_MFMA16 = 2 };
 
 constexpr int kNK = 16;          // subcarriers walked by one lane from its phase anchor
@@ -24,6 +24,10 @@ struct ExtrapOut {
   int32_t* first_out;   // pre-filled with T; lowered by atomic minimum
   double *q_pos, *q_vel, *q_acc;   // [R][T][4][3] interaction points and their time derivatives
   float* dop_rate;                 // [R][T] Doppler rate at f_c [Hz/s]
+  // power profiles (GEOM_POWER): [n_tb][n_dop], [n_tb][n_delay], [n_tb], cleared beforehand
+  double *pdfp, *pdp, *ptotal;
+  double dop_lo, dop_step, delay_lo, delay_step;
+  int spb, n_dop, n_delay, gate;
 };
 
 // Partition of H = sum over rays: a wave owns TTc instants x (KB * kNK) subcarriers of one
@@ -110,6 +114,40 @@ hipError_t launch_geom(const SceneView& sc, const RayClasses& rc, const void* po
                        hipStream_t st);
 hipError_t launch_cfr(const void* rec, const CfrArgs& a, int prec, void* out, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+// ---------------------------------------------------------------------------------------
+// Snapshot tracer.  One signature of candidate interaction sequences: the index of a
+// candidate is a mixed-radix number whose digit i (most significant first) picks the
+// primitive of interaction i: a wall (radix = walls, or walls - 1 after another wall, the
+// previous wall being skipped), an edge or a tile.  Ascending indices are lexicographic
+// in the primitive indices.
+struct TraceSig {
+  int32_t n, code;
+  int32_t kind[DRT_MAX_INT];
+  int64_t radix[DRT_MAX_INT];
+  int64_t count;
+};
+
+constexpr double kSegEps = 1e-7;    // an obstruction must cross a segment this far from its ends [m]
+constexpr double kFrontEps = 1e-9;  // a path's neighbours must lie this far in front of a wall [m]
+
+__host__ __device__ inline void trace_decode(const TraceSig& g, int64_t c, int32_t* prim) {
+  int32_t dig[DRT_MAX_INT] = {0, 0, 0, 0};
+  for (int i = g.n - 1; i >= 0; --i) {
+    dig[i] = int32_t(c % g.radix[i]);
+    c /= g.radix[i];
+  }
+  for (int i = 0; i < g.n; ++i) {
+    int32_t p = dig[i];
+    if (g.kind[i] == DRT_R && i > 0 && g.kind[i - 1] == DRT_R) p += (p >= prim[i - 1]) ? 1 : 0;
+    prim[i] = p;
+  }
+}
+
+hipError_t launch_trace_cand(const SceneView& sc, const TraceSig& g, int sig_id, uint64_t* keys, uint32_t cap,
+                             uint32_t* counter, hipStream_t st);
+hipError_t launch_trace_vis(const SceneView& sc, const TraceSig* d_sigs, const uint64_t* keys, uint32_t n,
+                            int n_planes, uint8_t* visible, double* length, hipStream_t st);
+
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st);
 hipError_t launch_reduce(const void* part, int G, size_t n, int prec, void* H, hipStream_t st);
 

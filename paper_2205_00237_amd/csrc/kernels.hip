@@ -59,6 +59,23 @@ struct RecN { float L, gr, gi, zr, zi, pad; };          // naive binary32: 24 B
 template <int PREC> struct GainT { using type = float; };
 template <> struct GainT<DRT_FP64> { using type = double; };
 
+// Adds each lane's value v to base[key] (lanes with key < 0 add nothing).  Lanes hold
+// consecutive instants of one ray, so equal keys come in runs: a segmented inclusive scan
+// over the 64 lanes sums each run, and the run's last lane issues one binary64 atomic add.
+__device__ __forceinline__ void wave_bin_add(double* base, int key, double v, int lane) {
+  const int prev = __shfl_up(key, 1), next = __shfl_down(key, 1);
+  const unsigned long long heads = __ballot(lane == 0 || key != prev);
+  // first lane of this lane's run: the highest run head at or below the lane
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const int start = 63 - __clzll((long long)(heads & upto));
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double u = __shfl_up(v, off);
+    if (lane - off >= start) v += u;
+  }
+  if (key >= 0 && (lane == 63 || key != next)) unsafeAtomicAdd(base + key, v);
+}
+
 // One wave: ray order[i] over the 64 instants of chunk c, where wave = 4 (nchunk (i / 4) + c) + i % 4.
 template <class F, int MODE, int PREC, int CLS>
 __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* order, int count,
@@ -148,7 +165,8 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   F fc = F(f_c);
   using G = typename GainT<PREC>::type;
   RayResult<F, G> res = with_signature_in<F, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
-    return eval_ray<F, G, N, DP, SCAT, false, MODE == GEOM_EXTRAP>(sc, ray, sl, TX, VTX, RX, VRX, fc);
+    return eval_ray<F, G, N, DP, SCAT, false, MODE == GEOM_EXTRAP || MODE == GEOM_POWER>(sc, ray, sl, TX, VTX,
+                                                                                         RX, VRX, fc);
   });
 
   if constexpr (MODE == GEOM_EXTRAP) {
@@ -173,6 +191,24 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
     }
     if (eo.valid) eo.valid[o] = res.ok ? 1 : 0;
     if (eo.in_bounds) eo.in_bounds[o] = res.in_bounds ? 1 : 0;
+  } else if constexpr (MODE == GEOM_POWER) {
+    // incoherent power sums (Sec. IV-A, IV-B): every lane takes part in the wave scans
+    const bool cnt = active && res.ok && (eo.gate == 0 || res.in_bounds);
+    const double gr = double(res.gain.re), gi = double(res.gain.im);
+    const double p = cnt ? gr * gr + gi * gi : 0.0;
+    const int tb = t / eo.spb;
+    if (eo.ptotal) wave_bin_add(eo.ptotal, cnt ? tb : -1, p, lane);
+    if (eo.pdfp) {
+      const double u = floor((double(res.dop) - eo.dop_lo) / eo.dop_step);
+      const bool in = cnt && u >= 0.0 && u < double(eo.n_dop);
+      wave_bin_add(eo.pdfp, in ? tb * eo.n_dop + int(u) : -1, p, lane);
+    }
+    if (eo.pdp) {
+      const double tau = double(res.L) / 299792458.0;
+      const double u = floor((tau - eo.delay_lo) / eo.delay_step);
+      const bool in = cnt && u >= 0.0 && u < double(eo.n_delay);
+      wave_bin_add(eo.pdp, in ? tb * eo.n_delay + int(u) : -1, p, lane);
+    }
   } else if constexpr (MODE == GEOM_ANCHOR_MFMA) {
     // phases of the first subcarrier, of one row block and of one subcarrier, each reduced
     // modulo one cycle in binary64 before rounding to binary32; the gain enters as its
@@ -886,6 +922,8 @@ hipError_t launch_geom(const SceneView& sc, const RayClasses& rc, const void* po
     return launch_geom_mode<GEOM_ANCHOR_MFMA>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
   if (mode == GEOM_KIN)
     return launch_geom_mode<GEOM_KIN>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
+  if (mode == GEOM_POWER)
+    return launch_geom_mode<GEOM_POWER>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
   return launch_geom_mode<GEOM_ANCHOR>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
 }
 

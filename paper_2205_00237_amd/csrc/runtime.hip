@@ -60,8 +60,29 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// A scene description held by value (the arrays of drt_scene_desc), kept with each
+// resident scene so that it can be carried to another instant and traced again.
+struct HostDesc {
+  double t0 = 0;
+  double tx_p[3]{}, tx_v[3]{}, tx_a[3]{}, rx_p[3]{}, rx_v[3]{}, rx_a[3]{};
+  int32_t nb = 0, nm = 0, np = 0, ne = 0, nt = 0, nr = 0;
+  std::vector<double> body_O0, body_v0, body_a, body_axis, body_w0, body_wdot;
+  std::vector<double> mat_eps_r, mat_sigma;
+  std::vector<uint8_t> mat_pec;
+  std::vector<int32_t> plane_body, plane_mat;
+  std::vector<double> plane_p0, plane_n0, plane_facet;       // facet: empty = every wall unbounded
+  std::vector<int32_t> edge_body;
+  std::vector<double> edge_a0, edge_e0, edge_t0, edge_n0, edge_wedge_n, edge_zlim;   // zlim may be empty
+  std::vector<int32_t> tile_body, tile_alpha;
+  std::vector<uint8_t> tile_model;
+  std::vector<double> tile_c0, tile_n0, tile_area, tile_S, tile_phase0;
+  std::vector<uint8_t> ray_nint, ray_kind, ray_pol;
+  std::vector<int32_t> ray_prim;
+};
+
 struct Scene {
   uint32_t id = 0;
+  HostDesc desc;
   SceneView view{};
   std::vector<DBody> bodies;     // host copies of the packed tables
   std::vector<DMat> mats;
@@ -845,13 +866,207 @@ int drt_destroy(drt_ctx* c) {
   return DRT_OK;
 }
 
-int drt_load_scene(drt_ctx* c, const drt_scene_desc* d, uint32_t* id) {
-  if (!c || !id) return fail(DRT_E_INVAL, "null context or id");
-  int st = set_device(c);
-  if (st) return st;
-  auto s = std::make_unique<Scene>();
-  st = validate_and_pack(d, *s);
-  if (st) return st;
+extern "C++" {
+template <class T>
+static std::vector<T> vcopy(const T* p, size_t n) {
+  return p ? std::vector<T>(p, p + n) : std::vector<T>();
+}
+template <class T>
+static const T* ptr_or_null(const std::vector<T>& v) {
+  return v.empty() ? nullptr : v.data();
+}
+}
+
+static HostDesc copy_desc(const drt_scene_desc* d) {
+  HostDesc h;
+  h.t0 = d->t0;
+  std::memcpy(h.tx_p, d->tx_p, 24);
+  std::memcpy(h.tx_v, d->tx_v, 24);
+  std::memcpy(h.tx_a, d->tx_a, 24);
+  std::memcpy(h.rx_p, d->rx_p, 24);
+  std::memcpy(h.rx_v, d->rx_v, 24);
+  std::memcpy(h.rx_a, d->rx_a, 24);
+  h.nb = d->n_bodies;
+  h.nm = d->n_mat;
+  h.np = d->n_planes;
+  h.ne = d->n_edges;
+  h.nt = d->n_tiles;
+  h.nr = d->n_rays;
+  const size_t nb = h.nb, nm = h.nm, np = h.np, ne = h.ne, nt = h.nt, nr = h.nr;
+  h.body_O0 = vcopy(d->body_O0, 3 * nb);
+  h.body_v0 = vcopy(d->body_v0, 3 * nb);
+  h.body_a = vcopy(d->body_a, 3 * nb);
+  h.body_axis = vcopy(d->body_axis, 3 * nb);
+  h.body_w0 = vcopy(d->body_w0, nb);
+  h.body_wdot = vcopy(d->body_wdot, nb);
+  h.mat_eps_r = vcopy(d->mat_eps_r, nm);
+  h.mat_sigma = vcopy(d->mat_sigma, nm);
+  h.mat_pec = vcopy(d->mat_pec, nm);
+  h.plane_body = vcopy(d->plane_body, np);
+  h.plane_mat = vcopy(d->plane_mat, np);
+  h.plane_p0 = vcopy(d->plane_p0, 3 * np);
+  h.plane_n0 = vcopy(d->plane_n0, 3 * np);
+  h.plane_facet = vcopy(d->plane_facet, 9 * np);
+  h.edge_body = vcopy(d->edge_body, ne);
+  h.edge_a0 = vcopy(d->edge_a0, 3 * ne);
+  h.edge_e0 = vcopy(d->edge_e0, 3 * ne);
+  h.edge_t0 = vcopy(d->edge_t0, 3 * ne);
+  h.edge_n0 = vcopy(d->edge_n0, 3 * ne);
+  h.edge_wedge_n = vcopy(d->edge_wedge_n, ne);
+  h.edge_zlim = vcopy(d->edge_zlim, 2 * ne);
+  h.tile_body = vcopy(d->tile_body, nt);
+  h.tile_alpha = vcopy(d->tile_alpha, nt);
+  h.tile_model = vcopy(d->tile_model, nt);
+  h.tile_c0 = vcopy(d->tile_c0, 3 * nt);
+  h.tile_n0 = vcopy(d->tile_n0, 3 * nt);
+  h.tile_area = vcopy(d->tile_area, nt);
+  h.tile_S = vcopy(d->tile_S, nt);
+  h.tile_phase0 = vcopy(d->tile_phase0, nt);
+  h.ray_nint = vcopy(d->ray_nint, nr);
+  h.ray_kind = vcopy(d->ray_kind, 4 * nr);
+  h.ray_pol = vcopy(d->ray_pol, 4 * nr);
+  h.ray_prim = vcopy(d->ray_prim, 4 * nr);
+  return h;
+}
+
+static drt_scene_desc desc_view(const HostDesc& h) {
+  drt_scene_desc d{};
+  d.t0 = h.t0;
+  std::memcpy(d.tx_p, h.tx_p, 24);
+  std::memcpy(d.tx_v, h.tx_v, 24);
+  std::memcpy(d.tx_a, h.tx_a, 24);
+  std::memcpy(d.rx_p, h.rx_p, 24);
+  std::memcpy(d.rx_v, h.rx_v, 24);
+  std::memcpy(d.rx_a, h.rx_a, 24);
+  d.n_bodies = h.nb;
+  d.body_O0 = ptr_or_null(h.body_O0);
+  d.body_v0 = ptr_or_null(h.body_v0);
+  d.body_a = ptr_or_null(h.body_a);
+  d.body_axis = ptr_or_null(h.body_axis);
+  d.body_w0 = ptr_or_null(h.body_w0);
+  d.body_wdot = ptr_or_null(h.body_wdot);
+  d.n_mat = h.nm;
+  d.mat_eps_r = ptr_or_null(h.mat_eps_r);
+  d.mat_sigma = ptr_or_null(h.mat_sigma);
+  d.mat_pec = ptr_or_null(h.mat_pec);
+  d.n_planes = h.np;
+  d.plane_body = ptr_or_null(h.plane_body);
+  d.plane_mat = ptr_or_null(h.plane_mat);
+  d.plane_p0 = ptr_or_null(h.plane_p0);
+  d.plane_n0 = ptr_or_null(h.plane_n0);
+  d.plane_facet = ptr_or_null(h.plane_facet);
+  d.n_edges = h.ne;
+  d.edge_body = ptr_or_null(h.edge_body);
+  d.edge_a0 = ptr_or_null(h.edge_a0);
+  d.edge_e0 = ptr_or_null(h.edge_e0);
+  d.edge_t0 = ptr_or_null(h.edge_t0);
+  d.edge_n0 = ptr_or_null(h.edge_n0);
+  d.edge_wedge_n = ptr_or_null(h.edge_wedge_n);
+  d.edge_zlim = ptr_or_null(h.edge_zlim);
+  d.n_tiles = h.nt;
+  d.tile_body = ptr_or_null(h.tile_body);
+  d.tile_alpha = ptr_or_null(h.tile_alpha);
+  d.tile_model = ptr_or_null(h.tile_model);
+  d.tile_c0 = ptr_or_null(h.tile_c0);
+  d.tile_n0 = ptr_or_null(h.tile_n0);
+  d.tile_area = ptr_or_null(h.tile_area);
+  d.tile_S = ptr_or_null(h.tile_S);
+  d.tile_phase0 = ptr_or_null(h.tile_phase0);
+  d.n_rays = h.nr;
+  d.ray_nint = ptr_or_null(h.ray_nint);
+  d.ray_kind = ptr_or_null(h.ray_kind);
+  d.ray_pol = ptr_or_null(h.ray_pol);
+  d.ray_prim = ptr_or_null(h.ray_prim);
+  d.ray_q0 = nullptr;
+  return d;
+}
+
+// The description carried to the instant t0 + t: terminals by eq. Taylor; every body's
+// reference point, velocity and angular speed advanced (Sec. III-A.1), and the primitives
+// of a moving body placed with its pose at t (rotation by theta = w0 t + wdot t^2 / 2 about
+// its fixed axis, Rodrigues' formula), so that the new description at its own t0 is the
+// old one at t0 + t.
+static HostDesc rebase(const HostDesc& d, double t) {
+  HostDesc r = d;
+  r.t0 = d.t0 + t;
+  const double h2 = 0.5 * t * t;
+  for (int k = 0; k < 3; ++k) {
+    r.tx_p[k] = d.tx_p[k] + d.tx_v[k] * t + d.tx_a[k] * h2;
+    r.tx_v[k] = d.tx_v[k] + d.tx_a[k] * t;
+    r.rx_p[k] = d.rx_p[k] + d.rx_v[k] * t + d.rx_a[k] * h2;
+    r.rx_v[k] = d.rx_v[k] + d.rx_a[k] * t;
+  }
+  struct BodyPose {
+    bool moving;
+    double O[3], O0[3], k[3], s, c1;
+  };
+  std::vector<BodyPose> bp(d.nb);
+  for (int b = 0; b < d.nb; ++b) {
+    BodyPose& B = bp[b];
+    const double *O0 = &d.body_O0[3 * b], *v0 = &d.body_v0[3 * b], *a = &d.body_a[3 * b];
+    const double w0 = d.body_w0[b], wd = d.body_wdot[b];
+    B.moving = w0 != 0 || wd != 0;
+    for (int k = 0; k < 3; ++k) B.moving = B.moving || v0[k] != 0 || a[k] != 0;
+    const double th = w0 * t + 0.5 * wd * t * t, hs = std::sin(0.5 * th);
+    B.s = std::sin(th);
+    B.c1 = 2.0 * hs * hs;
+    for (int k = 0; k < 3; ++k) {
+      B.O0[k] = O0[k];
+      B.k[k] = d.body_axis[3 * b + k];
+      B.O[k] = O0[k] + v0[k] * t + a[k] * h2;
+      r.body_O0[3 * b + k] = B.O[k];
+      r.body_v0[3 * b + k] = v0[k] + a[k] * t;
+    }
+    r.body_w0[b] = w0 + wd * t;
+  }
+  auto rot = [](const BodyPose& B, const double* v, double* out) {
+    const double kv[3] = {B.k[1] * v[2] - B.k[2] * v[1], B.k[2] * v[0] - B.k[0] * v[2], B.k[0] * v[1] - B.k[1] * v[0]};
+    const double kkv[3] = {B.k[1] * kv[2] - B.k[2] * kv[1], B.k[2] * kv[0] - B.k[0] * kv[2],
+                           B.k[0] * kv[1] - B.k[1] * kv[0]};
+    for (int k = 0; k < 3; ++k) out[k] = v[k] + B.s * kv[k] + B.c1 * kkv[k];
+  };
+  auto carry = [&](int b, const double* d0, double* out) {
+    if (bp[b].moving) rot(bp[b], d0, out);
+    else std::memmove(out, d0, 24);
+  };
+  auto place = [&](int b, const double* x0, double* out) {
+    if (!bp[b].moving) {
+      std::memmove(out, x0, 24);
+      return;
+    }
+    const double w[3] = {x0[0] - bp[b].O0[0], x0[1] - bp[b].O0[1], x0[2] - bp[b].O0[2]};
+    double rw[3];
+    rot(bp[b], w, rw);
+    for (int k = 0; k < 3; ++k) out[k] = bp[b].O[k] + rw[k];
+  };
+  for (int i = 0; i < d.np; ++i) {
+    const int b = d.plane_body[i];
+    place(b, &d.plane_p0[3 * i], &r.plane_p0[3 * i]);
+    carry(b, &d.plane_n0[3 * i], &r.plane_n0[3 * i]);
+    if (!d.plane_facet.empty()) {
+      place(b, &d.plane_facet[9 * i], &r.plane_facet[9 * i]);
+      carry(b, &d.plane_facet[9 * i + 3], &r.plane_facet[9 * i + 3]);
+      carry(b, &d.plane_facet[9 * i + 6], &r.plane_facet[9 * i + 6]);
+    }
+  }
+  for (int i = 0; i < d.ne; ++i) {
+    const int b = d.edge_body[i];
+    place(b, &d.edge_a0[3 * i], &r.edge_a0[3 * i]);
+    carry(b, &d.edge_e0[3 * i], &r.edge_e0[3 * i]);
+    carry(b, &d.edge_t0[3 * i], &r.edge_t0[3 * i]);
+    carry(b, &d.edge_n0[3 * i], &r.edge_n0[3 * i]);
+  }
+  for (int i = 0; i < d.nt; ++i) {
+    const int b = d.tile_body[i];
+    place(b, &d.tile_c0[3 * i], &r.tile_c0[3 * i]);
+    carry(b, &d.tile_n0[3 * i], &r.tile_n0[3 * i]);
+  }
+  return r;
+}
+
+// Upload a packed scene and make it resident.
+static int make_resident(drt_ctx* c, std::unique_ptr<Scene> s, uint32_t* id) {
+  int st;
   if ((st = upload(c, s->d_bodies, s->bodies.data(), s->bodies.size())) ||
       (st = upload(c, s->d_mats, s->mats.data(), s->mats.size())) ||
       (st = upload(c, s->d_planes, s->planes.data(), s->planes.size())) ||
@@ -882,6 +1097,17 @@ int drt_load_scene(drt_ctx* c, const drt_scene_desc* d, uint32_t* id) {
   return DRT_OK;
 }
 
+int drt_load_scene(drt_ctx* c, const drt_scene_desc* d, uint32_t* id) {
+  if (!c || !id) return fail(DRT_E_INVAL, "null context or id");
+  int st = set_device(c);
+  if (st) return st;
+  auto s = std::make_unique<Scene>();
+  st = validate_and_pack(d, *s);
+  if (st) return st;
+  s->desc = copy_desc(d);
+  return make_resident(c, std::move(s), id);
+}
+
 int drt_unload_scene(drt_ctx* c, uint32_t id) {
   if (!c) return fail(DRT_E_INVAL, "null context");
   std::lock_guard<std::mutex> g(c->mu);
@@ -899,6 +1125,235 @@ static Scene* find_scene(drt_ctx* c, uint32_t id) {
   std::lock_guard<std::mutex> g(c->mu);
   auto it = c->scenes.find(id);
   return it == c->scenes.end() ? nullptr : it->second.get();
+}
+
+// ---------------------------------------------------------------------------------------
+// snapshot tracing
+
+// The candidate signatures of a trace, in the order of the new scene's rays: line of sight;
+// 1..max_refl reflections; one diffraction with 0..max_refl_diff reflections, the edge at
+// every position from first to last; scattering.
+static std::vector<TraceSig> trace_signatures(const drt_trace_opts& o, int np, int ne, int nt) {
+  std::vector<std::vector<int>> kinds;
+  if (o.los) kinds.push_back({});
+  for (int n = 1; n <= o.max_refl; ++n) kinds.push_back(std::vector<int>(n, DRT_R));
+  for (int n = 0; n <= o.max_refl_diff; ++n)
+    for (int d = 0; d <= n; ++d) {
+      std::vector<int> k(n + 1, DRT_R);
+      k[d] = DRT_D;
+      kinds.push_back(k);
+    }
+  if (o.scattering) kinds.push_back({DRT_S});
+  std::vector<TraceSig> sigs;
+  for (const auto& k : kinds) {
+    TraceSig g{};
+    g.n = int(k.size());
+    uint8_t k8[DRT_MAX_INT] = {0, 0, 0, 0};
+    g.count = 1;
+    for (int i = 0; i < g.n; ++i) {
+      g.kind[i] = k[i];
+      k8[i] = uint8_t(k[i]);
+      const bool after_wall = i > 0 && k[i - 1] == DRT_R;
+      g.radix[i] = k[i] == DRT_R ? (after_wall ? np - 1 : np) : (k[i] == DRT_D ? ne : nt);
+      g.count = g.radix[i] > 0 ? g.count * g.radix[i] : 0;
+    }
+    int dpos;
+    g.code = sig_code(g.n, k8, &dpos);
+    sigs.push_back(g);
+  }
+  return sigs;
+}
+
+int drt_trace(drt_ctx* c, uint32_t scene, double t, const drt_trace_opts* o, uint32_t* new_scene,
+              drt_trace_info* info) {
+  if (!c || !o || !new_scene) return fail(DRT_E_INVAL, "null context, options or output");
+  if (!std::isfinite(t)) return fail(DRT_E_INVAL, "trace instant must be finite");
+  if (o->max_refl < 0 || o->max_refl > 3 || o->max_refl_diff < -1 || o->max_refl_diff > 2)
+    return fail(DRT_E_INVAL, "max_refl must be in 0..3 and max_refl_diff in -1..2");
+  Scene* s = find_scene(c, scene);
+  if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
+  int st = set_device(c);
+  if (st) return st;
+  HostDesc d = rebase(s->desc, t);
+  d.nr = 0;
+  d.ray_nint.clear();
+  d.ray_kind.clear();
+  d.ray_pol.clear();
+  d.ray_prim.clear();
+  // the primitives at the traced instant, on the device
+  Scene prim;
+  {
+    const drt_scene_desc dv = desc_view(d);
+    if ((st = validate_and_pack(&dv, prim))) return st;
+  }
+  struct Bufs {
+    drt_ctx* c;
+    DevBuf planes, edges, tiles, sigs, counter, keys, vis, len;
+    ~Bufs() {
+      for (DevBuf* b : {&planes, &edges, &tiles, &sigs, &counter, &keys, &vis, &len}) dev_free(c, *b);
+    }
+  } B{c};
+  const std::vector<TraceSig> sigs = trace_signatures(*o, d.np, d.ne, d.nt);
+  if ((st = upload(c, B.planes, prim.planes.data(), prim.planes.size())) ||
+      (st = upload(c, B.edges, prim.edges.data(), prim.edges.size())) ||
+      (st = upload(c, B.tiles, prim.tiles.data(), prim.tiles.size())) ||
+      (st = upload(c, B.sigs, sigs.data(), sigs.size())) || (st = dev_alloc(c, B.counter, 4)))
+    return st;
+  SceneView sv = prim.view;
+  sv.planes = (const DPlane*)B.planes.p;
+  sv.edges = (const DEdge*)B.edges.p;
+  sv.tiles = (const DTile*)B.tiles.p;
+  int64_t candidates = 0;
+  for (const auto& g : sigs) candidates += g.count;
+  const hipStream_t hs = nullptr;
+  uint32_t cap = uint32_t(std::min<int64_t>(std::max<int64_t>(candidates, 1), int64_t(1) << 20)), n = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    dev_free(c, B.keys);
+    if ((st = dev_alloc(c, B.keys, size_t(cap) * sizeof(uint64_t)))) return st;
+    HIP_OK(launch_fill_i32((int32_t*)B.counter.p, 1, 0, hs));
+    for (size_t i = 0; i < sigs.size(); ++i)
+      HIP_OK(launch_trace_cand(sv, sigs[i], int(i), (uint64_t*)B.keys.p, cap, (uint32_t*)B.counter.p, hs));
+    HIP_OK(hipMemcpy(&n, B.counter.p, 4, hipMemcpyDeviceToHost));
+    if (n <= cap) break;
+    if (pass == 1) return fail(DRT_E_DEVICE, "survivor count changed between identical passes");
+    cap = n;    // rerun with room for every survivor
+  }
+  if ((st = dev_alloc(c, B.vis, std::max<size_t>(n, 1))) || (st = dev_alloc(c, B.len, std::max<size_t>(n, 1) * 8)))
+    return st;
+  HIP_OK(launch_trace_vis(sv, (const TraceSig*)B.sigs.p, (const uint64_t*)B.keys.p, n, d.np, (uint8_t*)B.vis.p,
+                          (double*)B.len.p, hs));
+  std::vector<uint64_t> keys(n);
+  std::vector<uint8_t> vis(n);
+  if (n) {
+    HIP_OK(hipMemcpy(keys.data(), B.keys.p, size_t(n) * 8, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(vis.data(), B.vis.p, n, hipMemcpyDeviceToHost));
+  }
+  std::vector<uint64_t> found;
+  for (uint32_t i = 0; i < n; ++i)
+    if (vis[i]) found.push_back(keys[i]);
+  std::sort(found.begin(), found.end());
+  drt_trace_info inf{};
+  inf.candidates = candidates;
+  inf.geometric = n;
+  d.nr = int32_t(found.size());
+  d.ray_nint.assign(found.size(), 0);
+  d.ray_kind.assign(4 * found.size(), 0);
+  d.ray_pol.assign(4 * found.size(), 0);
+  d.ray_prim.assign(4 * found.size(), 0);
+  for (size_t r = 0; r < found.size(); ++r) {
+    const TraceSig& g = sigs[found[r] >> 40];
+    int32_t pr[DRT_MAX_INT];
+    trace_decode(g, int64_t(found[r] & ((uint64_t(1) << 40) - 1)), pr);
+    d.ray_nint[r] = uint8_t(g.n);
+    for (int i = 0; i < g.n; ++i) {
+      d.ray_kind[4 * r + i] = uint8_t(g.kind[i]);
+      d.ray_prim[4 * r + i] = pr[i];
+      int pol = DRT_PERP;
+      if (g.kind[i] == DRT_R) pol = std::fabs(d.plane_n0[3 * pr[i] + 2]) > 0.5 ? DRT_PAR : DRT_PERP;
+      if (g.kind[i] == DRT_D) pol = std::fabs(d.edge_e0[3 * pr[i] + 2]) > 0.5 ? DRT_PERP : DRT_PAR;
+      d.ray_pol[4 * r + i] = uint8_t(pol);
+    }
+    inf.n_los += g.n == 0;
+    inf.n_scat += g.n == 1 && g.kind[0] == DRT_S;
+    bool has_d = false;
+    for (int i = 0; i < g.n; ++i) has_d = has_d || g.kind[i] == DRT_D;
+    inf.n_diff += has_d;
+    inf.n_refl += g.n > 0 && g.kind[0] != DRT_S && !has_d;
+  }
+  inf.n_paths = d.nr;
+  auto out = std::make_unique<Scene>();
+  {
+    const drt_scene_desc dv = desc_view(d);
+    if ((st = validate_and_pack(&dv, *out))) return st;
+  }
+  out->desc = std::move(d);
+  if ((st = make_resident(c, std::move(out), new_scene))) return st;
+  if (info) *info = inf;
+  return DRT_OK;
+}
+
+int drt_segments(drt_ctx* c, uint32_t scene, const drt_time_grid* tg, double f_c, const drt_trace_opts* topts,
+                 const drt_refresh_opts* ropts, int32_t max_segments, int32_t* seg_start, int32_t* seg_len,
+                 uint32_t* seg_scene, int32_t* n_segments) {
+  if (!c || !tg || !topts || !ropts || !n_segments || (max_segments > 0 && (!seg_start || !seg_len || !seg_scene)))
+    return fail(DRT_E_INVAL, "null argument");
+  if (tg->n_steps < 0 || !(tg->dt > 0) || !std::isfinite(tg->dt)) return fail(DRT_E_INVAL, "bad time grid");
+  if (!(f_c > 0)) return fail(DRT_E_INVAL, "carrier must be > 0");
+  if (!(ropts->threshold_db >= 0) || ropts->max_steps < 1 || ropts->min_steps < 1 ||
+      ropts->min_steps > ropts->max_steps)
+    return fail(DRT_E_INVAL, "need threshold_db >= 0 and 1 <= min_steps <= max_steps");
+  if (!find_scene(c, scene)) return fail(DRT_E_NOTFOUND, "scene %u", scene);
+  int st = set_device(c);
+  if (st) return st;
+  std::vector<uint32_t> made;
+  auto undo = [&](int code) {
+    const std::string msg = g_last_error;
+    for (uint32_t id : made) (void)drt_unload_scene(c, id);
+    g_last_error = msg;
+    return code;
+  };
+  const int T = tg->n_steps;
+  int j = 0, k = 0;
+  while (j < T) {
+    if (k == max_segments) return undo(fail(DRT_E_INVAL, "more than %d segments", max_segments));
+    uint32_t sid = 0;
+    drt_trace_info inf{};
+    if ((st = drt_trace(c, scene, double(j) * tg->dt, topts, &sid, &inf))) return undo(st);
+    made.push_back(sid);
+    const int m = std::min(ropts->max_steps, T - j);
+    int len = m;
+    const int R = inf.n_paths;
+    if (R > 0) {
+      DevBuf gain, fo;
+      struct Free {
+        drt_ctx* c;
+        DevBuf *a, *b;
+        ~Free() { dev_free(c, *a), dev_free(c, *b); }
+      } fr{c, &gain, &fo};
+      if ((st = dev_alloc(c, gain, size_t(R) * 16)) || (st = dev_alloc(c, fo, size_t(R) * 4))) return undo(st);
+      drt_ray_out o1{}, om{};
+      o1.gain = gain.p;
+      om.first_out = (int32_t*)fo.p;
+      const drt_time_grid t1{tg->dt, 1}, tm{tg->dt, m};
+      if ((st = drt_extrapolate(c, sid, R, &t1, f_c, DRT_FP64, &o1, nullptr)) ||
+          (st = drt_extrapolate(c, sid, R, &tm, f_c, DRT_FP64, &om, nullptr)))
+        return undo(st);
+      std::vector<double> g(2 * size_t(R));
+      std::vector<int32_t> f(R);
+      if (hipMemcpy(g.data(), gain.p, size_t(R) * 16, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(f.data(), fo.p, size_t(R) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return undo(fail(DRT_E_DEVICE, "copying the monitor's results"));
+      double pmax = 0;
+      for (int r = 0; r < R; ++r) pmax = std::max(pmax, g[2 * r] * g[2 * r] + g[2 * r + 1] * g[2 * r + 1]);
+      const double floor_p = pmax * std::pow(10.0, -ropts->threshold_db / 10.0);
+      int first = m;
+      for (int r = 0; r < R; ++r)
+        if (g[2 * r] * g[2 * r] + g[2 * r + 1] * g[2 * r + 1] >= floor_p) first = std::min(first, f[r]);
+      len = std::min(m, std::max(ropts->min_steps, first));
+    }
+    seg_start[k] = j;
+    seg_len[k] = len;
+    seg_scene[k] = sid;
+    ++k;
+    j += len;
+  }
+  *n_segments = k;
+  return DRT_OK;
+}
+
+int drt_scene_rays(drt_ctx* c, uint32_t scene, int32_t cap, int32_t* n_rays, uint8_t* nint, uint8_t* kind,
+                   int32_t* prim, uint8_t* pol) {
+  if (!c || !n_rays || cap < 0) return fail(DRT_E_INVAL, "null context or count, or negative capacity");
+  Scene* s = find_scene(c, scene);
+  if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
+  const HostDesc& h = s->desc;
+  *n_rays = h.nr;
+  const size_t m = size_t(std::min(cap, h.nr));
+  if (nint && m) std::memcpy(nint, h.ray_nint.data(), m);
+  if (kind && m) std::memcpy(kind, h.ray_kind.data(), 4 * m);
+  if (prim && m) std::memcpy(prim, h.ray_prim.data(), 16 * m);
+  if (pol && m) std::memcpy(pol, h.ray_pol.data(), 4 * m);
+  return DRT_OK;
 }
 
 int drt_extrapolate(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg, double f_c,
@@ -955,6 +1410,60 @@ int drt_extrapolate(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_g
                          AnchorParams{0.0, 0.0, 0.0}, hs);
     }, class_kernels(rc, T)));
   }
+  return DRT_OK;
+}
+
+int drt_power_profiles(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg, double f_c,
+                       int32_t prec, const drt_bins* bins, const drt_power_out* out, void* stream) {
+  if (!c || !bins || !out) return fail(DRT_E_INVAL, "null context, bins or output");
+  Scene* s = find_scene(c, scene);
+  if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
+  int st;
+  if ((st = check_grid(tg, n_rays, *s)) || (st = check_prec(prec))) return st;
+  if (!(f_c > 0)) return fail(DRT_E_INVAL, "carrier must be > 0");
+  if (bins->steps_per_bin < 1) return fail(DRT_E_INVAL, "steps_per_bin must be >= 1");
+  if (!(bins->dop_step > 0) || !(bins->delay_step > 0) || !std::isfinite(bins->dop_lo) ||
+      !std::isfinite(bins->delay_lo) || !std::isfinite(bins->dop_step) || !std::isfinite(bins->delay_step))
+    return fail(DRT_E_INVAL, "bin origins must be finite and steps finite and > 0");
+  if (bins->n_dop < 0 || bins->n_delay < 0) return fail(DRT_E_INVAL, "negative bin count");
+  const int T = tg->n_steps;
+  const int64_t n_tb = (int64_t(T) + bins->steps_per_bin - 1) / bins->steps_per_bin;
+  if (n_tb * bins->n_dop > INT32_MAX || n_tb * bins->n_delay > INT32_MAX)
+    return fail(DRT_E_INVAL, "more than 2^31 - 1 profile bins");
+  double* pdfp = bins->n_dop > 0 ? out->pdfp : nullptr;
+  double* pdp = bins->n_delay > 0 ? out->pdp : nullptr;
+  if (n_tb > 0 && ((bins->n_dop > 0 && !pdfp) || (bins->n_delay > 0 && !pdp)))
+    return fail(DRT_E_INVAL, "null profile output with a nonzero bin count");
+  if ((st = set_device(c))) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  if (n_tb == 0) return DRT_OK;
+  if (pdfp) HIP_OK(launch_zero(pdfp, size_t(n_tb) * bins->n_dop * sizeof(double), hs));
+  if (pdp) HIP_OK(launch_zero(pdp, size_t(n_tb) * bins->n_delay * sizeof(double), hs));
+  if (out->total) HIP_OK(launch_zero(out->total, size_t(n_tb) * sizeof(double), hs));
+  if (n_rays == 0 || (!pdfp && !pdp && !out->total)) return DRT_OK;
+  std::lock_guard<std::mutex> g(c->scratch_mu);
+  Scratch& sc = c->scratch[hs];
+  if ((st = ensure_scratch(c, sc, pose_bytes(s->view.n_bodies, T, prec), hs))) return st;
+  const RayClasses rc = classes(*s, n_rays);
+  HIP_OK(timed(c, DRT_K_POSE, hs, [&] {
+    return launch_pose((const DBody*)s->d_bodies.p, s->view.n_bodies, T, tg->dt, prec, sc.buf.p, hs);
+  }));
+  ExtrapOut eo{};
+  eo.pdfp = pdfp;
+  eo.pdp = pdp;
+  eo.ptotal = out->total;
+  eo.dop_lo = bins->dop_lo;
+  eo.dop_step = bins->dop_step;
+  eo.delay_lo = bins->delay_lo;
+  eo.delay_step = bins->delay_step;
+  eo.spb = bins->steps_per_bin;
+  eo.n_dop = bins->n_dop;
+  eo.n_delay = bins->n_delay;
+  eo.gate = bins->in_bounds_only != 0;
+  HIP_OK(timed(c, DRT_K_GEOM, hs, [&] {
+    return launch_geom(device_view(*s), rc, sc.buf.p, T, tg->dt, f_c, n_rays, prec, GEOM_POWER, eo, nullptr,
+                       AnchorParams{0.0, 0.0, 0.0}, hs);
+  }, class_kernels(rc, T)));
   return DRT_OK;
 }
 

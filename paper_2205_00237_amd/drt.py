@@ -77,6 +77,55 @@ class Context:
                              {k: v.data_ptr() for k, v in out.items()}, _stream(stream))
         return out
 
+    def trace(self, sid, t=0.0, max_refl=2, max_refl_diff=1, scattering=True, los=True):
+        """Snapshot trace at the scene's t0 + t: a new resident scene (the primitives carried
+        to that instant, one ray per path found).  Returns (new scene id, info dict)."""
+        new, info = _abi.drt_trace(self.ctx, sid, t, max_refl, max_refl_diff, scattering, los)
+        self.n_rays[new] = info["n_paths"]
+        return new, info
+
+    def segments(self, sid, tgrid, f_c, threshold_db=10.0, max_steps=200, min_steps=1, **trace_opts):
+        """Multipath lifetimes over the time grid, each traced afresh at its start:
+        [(first instant, length, resident scene id)]; the caller unloads the scenes."""
+        segs = _abi.drt_segments(self.ctx, sid, tgrid.dt, tgrid.n_steps, f_c, trace_opts, threshold_db,
+                                 max_steps, min_steps)
+        for _, _, s in segs:
+            self.n_rays[s] = int(_abi.drt_scene_rays(self.ctx, s)[0].shape[0])
+        return segs
+
+    def cfr_segments(self, segs, tgrid, fgrid, precision=DRT_SPLIT, out=None, stream=None):
+        """H over the whole time grid, rows of each segment from the scene traced at its start."""
+        T, K = int(tgrid.n_steps), int(fgrid.n_sub)
+        if out is None:
+            out = torch.empty((T, K), dtype=torch.complex128 if precision == DRT_FP64 else torch.complex64,
+                              device=self.device)
+        for j0, n, s in segs:
+            rows = out[j0:j0 + n]
+            _abi.drt_cfr(self.ctx, s, self.n_rays[s], tgrid.dt, n, fgrid.f_c, fgrid.bandwidth, K, precision,
+                         rows.data_ptr(), _stream(stream))
+        return out
+
+    def scene_rays(self, sid):
+        """Interaction sequences of a resident scene: nint, kind, prim, pol (numpy)."""
+        return _abi.drt_scene_rays(self.ctx, sid)
+
+    def power_profiles(self, sid, tgrid, f_c, bins, precision=DRT_SPLIT, n_rays=None, stream=None, out=None):
+        """Power-Doppler profile pdfp [n_tb][n_dop], power-delay profile pdp [n_tb][n_delay] and
+        per-time-bin total [n_tb] as binary64 device tensors; bins: dict of steps_per_bin,
+        n_dop, dop_lo, dop_step, n_delay, delay_lo, delay_step and optionally in_bounds_only.
+        `out` may pass a dict of preallocated tensors (any subset) to write instead."""
+        R = self.n_rays[sid] if n_rays is None else int(n_rays)
+        T = int(tgrid.n_steps)
+        if out is None:
+            n_tb = (T + int(bins["steps_per_bin"]) - 1) // max(int(bins["steps_per_bin"]), 1)
+            f8 = dict(dtype=torch.float64, device=self.device)
+            out = {"pdfp": torch.empty((n_tb, int(bins["n_dop"])), **f8),
+                   "pdp": torch.empty((n_tb, int(bins["n_delay"])), **f8),
+                   "total": torch.empty((n_tb,), **f8)}
+        _abi.drt_power_profiles(self.ctx, sid, R, tgrid.dt, T, f_c, precision, bins,
+                                {k: v.data_ptr() for k, v in out.items()}, _stream(stream))
+        return out
+
     def cfr(self, sid, tgrid, fgrid, precision=DRT_SPLIT, n_rays=None, out=None, stream=None):
         """H(t_j, f_k) as a device tensor [n_steps][n_sub] (complex128 for FP64, else complex64)."""
         R = self.n_rays[sid] if n_rays is None else int(n_rays)

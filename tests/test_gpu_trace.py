@@ -1,0 +1,191 @@
+"""Snapshot tracing on the GPU through the C ABI against the oracle tracer: the shoebox room
+(image counts 1, 6, 18, 38), the screen scenes (obstruction closed forms), the moving-box
+scenes at two instants (the traced scene carried to the instant, checked by extrapolating it
+against the original scene's motion), the tiny scene with its scattering tiles, and the
+urban scene (320 walls, 480 edges): every sequence with up to two reflections or one
+diffraction and one reflection against the oracle's full trace, three-reflection paths
+against the oracle's existence test on every path found and on 20 000 sampled candidates.
+
+Path sets must be identical (no candidate of these scenes lies within rounding of a facet,
+segment or front-side boundary), and each path's length at the traced instant within
+1e-9 m of the oracle's."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from oracle.tracer import path_exists, moved_scene, signatures, candidates
+from paper_2205_00237_amd import scenes
+from paper_2205_00237_amd.scenes import KIND_R, KIND_D, KIND_S
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, __file__.rsplit("/", 1)[0])
+from test_oracle_tracer import _shoebox, _screen_scene, _wedge_world_scene, ROOM  # noqa: E402
+from test_oracle_bruteforce import _world  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_00237_amd.drt import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def gpu_paths(ctx, sid):
+    nint, kind, prim, pol = ctx.scene_rays(sid)
+    out = []
+    for r in range(len(nint)):
+        n = int(nint[r])
+        out.append((tuple(int(x) for x in kind[r, :n]), tuple(int(x) for x in prim[r, :n]),
+                    tuple(int(x) for x in pol[r, :n])))
+    return out
+
+
+def gpu_lengths(ctx, sid, f_c=5.9e9):
+    if ctx.n_rays[sid] == 0:
+        return np.zeros(0)
+    out = ctx.extrapolate(sid, scenes.TimeGrid(1e-3, 1), f_c, precision=0)
+    assert out["valid"].bool().all() and out["in_bounds"].bool().all()
+    return out["L"][:, 0].cpu().numpy()
+
+
+def check_trace(ctx, scene, t, where, **opts):
+    sid = ctx.load_scene(scene)
+    new, info = ctx.trace(sid, t, **opts)
+    got = gpu_paths(ctx, new)
+    ref = oracle.trace(scene, t, **opts)
+    want = [(k, p, q) for k, p, q, _ in ref]
+    if got != want:
+        missing = [x for x in want if x not in got][:5]
+        extra = [x for x in got if x not in want][:5]
+        raise AssertionError(f"{where}: {len(got)} paths vs {len(want)}; missing {missing}, extra {extra}")
+    if want:
+        L = gpu_lengths(ctx, new)
+        dL = np.abs(L - np.array([l for *_, l in ref])).max()
+        assert dL < 1e-9, f"{where}: |dL| {dL}"
+    assert info["n_paths"] == len(want)
+    say(f"{where}: {len(want)} paths, {info['candidates']} candidates, {info['geometric']} geometric")
+    ctx.unload_scene(sid)
+    return new, ref, info
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_shoebox(ctx, seed):
+    rng = np.random.default_rng(seed)
+    s = _shoebox(rng.uniform(0.3, 0.9, 3) * ROOM, rng.uniform(0.1, 0.9, 3) * ROOM)
+    new, ref, info = check_trace(ctx, s, 0.0, f"shoebox {seed}", max_refl=3, max_refl_diff=-1,
+                                 scattering=False, los=True)
+    counts = [sum(1 for k, *_ in ref if len(k) == n) for n in range(4)]
+    assert counts == [1, 6, 18, 38]
+    assert (info["n_los"], info["n_refl"], info["n_diff"], info["n_scat"]) == (1, 62, 0, 0)
+    ctx.unload_scene(new)
+
+
+def test_screens(ctx):
+    for centre, want in (((10, 0, 1.5), [(KIND_R,)]), ((5, 3, 1.5), [()]), ((5, 4.5, 1.5), [(), (KIND_R,)])):
+        s = _screen_scene(centre)
+        new, ref, _ = check_trace(ctx, s, 0.0, f"screen {centre}", max_refl=1, max_refl_diff=-1,
+                                  scattering=False, los=True)
+        assert [k for k, *_ in ref] == want
+        ctx.unload_scene(new)
+    new, ref, _ = check_trace(ctx, _screen_scene((5, 4.5, 1.5)), 0.0, "screen edge", max_refl=0,
+                              max_refl_diff=0, scattering=False, los=False)
+    assert [k for k, *_ in ref] == [(KIND_D,)]
+    ctx.unload_scene(new)
+
+
+@pytest.mark.parametrize("seed,t", [(0, 0.0), (1, 0.37), (1, 0.81)])
+def test_moving_boxes_and_carried_scene(ctx, seed, t):
+    s, _, _ = _wedge_world_scene(_world(seed))
+    new, ref, _ = check_trace(ctx, s, t, f"world {seed} t={t}", max_refl=2, max_refl_diff=1,
+                              scattering=False, los=True)
+    # the traced scene lives at t0 + t: extrapolating it by tau gives the original scene's
+    # geometry at t + tau (oracle on the original scene with the traced rays)
+    s2 = dict(s)
+    n = len(ref)
+    s2["ray_nint"] = np.array([len(k) for k, *_ in ref], np.uint8)
+    for key, dt in (("ray_kind", np.uint8), ("ray_prim", np.int32), ("ray_pol", np.uint8)):
+        s2[key] = np.zeros((n, 4), dt)
+    for r, (k, p, q, _) in enumerate(ref):
+        s2["ray_kind"][r, :len(k)] = k
+        s2["ray_prim"][r, :len(k)] = p
+        s2["ray_pol"][r, :len(k)] = q
+    tau = np.arange(40) * 5e-3
+    ex = oracle.extrapolate(s2, t + tau, 5.9e9)
+    out = ctx.extrapolate(new, scenes.TimeGrid(5e-3, 40), 5.9e9, precision=0)
+    v = out["valid"].cpu().numpy().astype(bool)
+    assert np.array_equal(v, ex["valid"])
+    dL = np.abs(out["L"].cpu().numpy() - ex["L"])[v].max()
+    dD = np.abs(out["dop"].cpu().numpy().astype(np.float64) - ex["dop"])[v].max()
+    assert dL < 1e-9 and dD < 1e-3, (dL, dD)
+    ctx.unload_scene(new)
+
+
+def test_tiny_scene_with_tiles(ctx):
+    s, tg, fg = scenes.config1()
+    for t in (0.0, 0.05):
+        new, ref, info = check_trace(ctx, s, t, f"tiny t={t}", max_refl=2, max_refl_diff=1, scattering=True,
+                                     los=True)
+        assert info["n_scat"] == sum(1 for k, *_ in ref if k == (KIND_S,)) > 0
+        ctx.unload_scene(new)
+
+
+def test_urban(ctx):
+    s, tg, fg = scenes.config2()
+    say("urban: up to two reflections, one diffraction with one reflection")
+    new, ref, info = check_trace(ctx, s, 0.0, "urban", max_refl=2, max_refl_diff=1, scattering=False, los=True)
+    assert info["n_paths"] >= 10
+    ctx.unload_scene(new)
+    say("urban: three reflections")
+    sid = ctx.load_scene(s)
+    new, info = ctx.trace(sid, 0.0, max_refl=3, max_refl_diff=-1, scattering=False, los=False)
+    got = [(k, p) for k, p, _ in gpu_paths(ctx, new) if len(k) == 3]
+    ms = moved_scene(s, 0.0)
+    kinds = (KIND_R,) * 3
+    if got:
+        ok, L, _ = path_exists(ms, kinds, np.array([p for _, p in got]))
+        assert ok.all(), f"{(~ok).sum()} of {len(got)} three-reflection paths are not paths"
+        dL = np.abs(gpu_lengths(ctx, new)[[i for i, (k, _, _) in enumerate(gpu_paths(ctx, new)) if len(k) == 3]] - L)
+        assert dL.max() < 1e-9
+    rng = np.random.default_rng(7)
+    P = ms["p"].shape[0]
+    cand = rng.integers(0, P, size=(60000, 3))
+    cand = cand[(cand[:, 0] != cand[:, 1]) & (cand[:, 1] != cand[:, 2])][:20000]
+    ok, _, _ = path_exists(ms, kinds, cand)
+    found = set(p for _, p in got)
+    missed = [tuple(int(x) for x in c) for c in cand[ok] if tuple(int(x) for x in c) not in found]
+    assert not missed, f"sampled three-reflection paths missing on the GPU: {missed[:5]}"
+    say(f"urban R3: {len(got)} paths found, {ok.sum()} of {len(cand)} sampled candidates are paths; "
+        f"{info['candidates']} candidates")
+    ctx.unload_scene(new)
+    ctx.unload_scene(sid)
+
+
+def test_trace_errors(ctx):
+    from paper_2205_00237_amd._abi import DrtError
+    s, _, _ = scenes.config1()
+    sid = ctx.load_scene(s)
+    for bad in (dict(max_refl=4), dict(max_refl=-1), dict(max_refl_diff=3), dict(max_refl_diff=-2)):
+        with pytest.raises(DrtError):
+            ctx.trace(sid, 0.0, **bad)
+    with pytest.raises(DrtError):
+        ctx.trace(sid, float("nan"))
+    with pytest.raises(DrtError):
+        ctx.trace(987654, 0.0)
+    # nothing asked for: an empty scene with the carried primitives
+    new, info = ctx.trace(sid, 0.2, max_refl=0, max_refl_diff=-1, scattering=False, los=False)
+    assert info["n_paths"] == 0 and ctx.scene_rays(new)[0].shape == (0,)
+    ctx.unload_scene(new)
+    ctx.unload_scene(sid)

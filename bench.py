@@ -8,8 +8,11 @@ extrapolation and field coefficients, and the ray sum H(t, f), in split precisio
 metric is ray x time x frequency samples of H per second, with inputs resident in device
 memory.  Beside it: the binary64 GPU path on the same workload, the kernel-level roofline
 of the dominant kernel (timed with HIP events on its own stream), the CPU oracle on a
-bounded sample, and the serving mix (4096 Poisson requests over 64 resident scenes) with
-p50 / p99 latency.  Prints one JSON line.
+bounded sample, the serving mix (4096 Poisson requests over 64 resident scenes) with
+p50 / p99 latency, and the other calls on the same scene: drt_extrapolate with the
+validity monitor, the interaction-point kinematics, the power-Doppler and power-delay
+profiles, the snapshot trace and the multipath-lifetime refresh, and H by the non-uniform
+FFT.  Prints one JSON line.
 """
 import argparse
 import json
@@ -245,6 +248,40 @@ def main():
                 "gated_counted_power": counted}
     log(f"power profiles: {profiles}")
     del pp
+    # snapshot tracing (the conventional RT that DRT extrapolates) and the lifetime refresh;
+    # against it, the paper's comparison: a snapshot trace at every instant (timed on 20
+    # instants spread over the span, scaled to all of them) versus DRT, a trace per lifetime
+    # plus extrapolation, both followed by the same ray sum over the span
+    topts = dict(max_refl=3, max_refl_diff=1, scattering=False, los=True)
+    t_tr = []
+    for _ in range(4):
+        t = time.perf_counter()
+        new, info = ctx.trace(sid, 0.0, **topts)
+        t_tr.append(time.perf_counter() - t)
+        ctx.unload_scene(new)
+    trace_s = sorted(t_tr[1:])[1]
+    sopts = dict(max_refl=2, max_refl_diff=1, scattering=False, los=True)
+    t = time.perf_counter()
+    segs = ctx.segments(sid, tg, fg.f_c, threshold_db=10.0, max_steps=250, **sopts)
+    seg_s = time.perf_counter() - t
+    Hs = torch.empty((T, K), dtype=torch.complex64, device="cuda")
+    sec_hs = timed_steps(lambda: ctx.cfr_segments(segs, tg, fg, DRT_SPLIT, out=Hs), 5, 1, torch)
+    t = time.perf_counter()
+    for j in range(0, T, T // 20):
+        new, _ = ctx.trace(sid, j * tg.dt, **sopts)
+        ctx.unload_scene(new)
+    snap_s = (time.perf_counter() - t) / len(range(0, T, T // 20)) * T
+    for _, _, s_id in segs:
+        ctx.unload_scene(s_id)
+    tracer = {"trace_ms": trace_s * 1e3, "orders": "LoS, 1-3 reflections, 1 diffraction with 0-1 reflections",
+              "candidates": info["candidates"], "candidates_per_s": info["candidates"] / trace_s,
+              "geometric": info["geometric"], "paths": info["n_paths"],
+              "segments": len(segs), "segment_instants": [n for _, n, _ in segs],
+              "segments_s": seg_s, "cfr_over_segments_ms": sec_hs * 1e3,
+              "snapshot_trace_every_instant_s": snap_s,
+              "drt_vs_snapshot_speedup": (snap_s + sec_hs) / (seg_s + sec_hs)}
+    log(f"tracer: {tracer}")
+    del Hs
     sec64 = None
     if not args.no_fp64:
         H64 = torch.empty((T, K), dtype=torch.complex128, device="cuda")
@@ -254,6 +291,24 @@ def main():
         prof64 = ctx.profile_read(reset=True)
         ctx.profile(False)
         log(f"fp64: {sec64 * 1e3:.3f} ms/step, kernels {prof64}")
+    # the same H by the type-1 non-uniform FFT along f (binary64, kernel accuracy 1e-9 of
+    # sum |a|): a variant with per-instant work R w + 5 M log2 M instead of R K; its error is
+    # taken against the binary64 direct sum
+    Hn = torch.empty((T, K), dtype=torch.complex128, device="cuda")
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    sec_nu = timed_steps(lambda: ctx.cfr_nufft(sid, tg, fg, eps=1e-9, out=Hn), args.steps, 2, torch)
+    prof_nu = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    nufft = {"ms_per_step": sec_nu * 1e3, "samples_per_s": samples / sec_nu, "eps": 1e-9, "dtype": "f64",
+             "kernels": {k: {"avg_ms": v[0] / max(1, v[1]), "launches": v[1]} for k, v in prof_nu.items() if v[1]},
+             "per_instant_work": "spread 5000 rays x 10 kernel points, FFT of 2048, 1024 outputs"}
+    if sec64:
+        ref_rms = float(torch.sqrt(torch.mean(torch.abs(H64) ** 2)))
+        nufft["max_err_vs_fp64_direct_rel_rms"] = float(torch.max(torch.abs(Hn - H64))) / ref_rms
+        nufft["speedup_vs_fp64_direct"] = sec64 / sec_nu
+    log(f"nufft: {nufft}")
+    del Hn
 
     # dominant kernel of the split step (largest time per launch), against its roofline;
     # its average launch time comes from HIP events recorded on the stream it runs on
@@ -295,6 +350,8 @@ def main():
         "extrapolate": extrap,
         "kinematics": kinematics,
         "power_profiles": profiles,
+        "tracer": tracer,
+        "nufft": nufft,
         "kernels": kernels,
         "scene_load_s": load_s,
     }

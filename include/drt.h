@@ -286,6 +286,18 @@ int drt_power_profiles(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_t
 int drt_cfr(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_grid *tg,
             const drt_freq_grid *fg, int32_t precision, void *H, void *stream);
 
+/* The same H as drt_cfr in binary64, by a type-1 non-uniform FFT along the subcarrier grid
+ * (per instant about R w + 5 M log2 M operations instead of R K): per instant, each ray's
+ * coefficient c = a exp(-j 2 pi frac(f_c L / c)) is spread at x = frac(df L / c) onto a
+ * periodic grid of M points (the smallest power of two >= 2K and >= 2w) with an exponential-of-
+ * semicircle kernel of w points (w = ceil(-log10 eps) + 1, 2..16, shape 2.30 w), the grid
+ * is Fourier transformed and divided by the kernel's transform.  eps (1e-15 .. 1e-1) is the
+ * target error of each H[j][k] relative to sum_r |a_r(t_j)|.  H: device [n_steps][n_sub]
+ * complex128, on `stream`.  Errors: DRT_E_INVAL for n_sub > 2048 or eps out of range; those
+ * of drt_cfr.  Deterministic up to the order of the atomic additions into the grid. */
+int drt_cfr_nufft(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_grid *tg,
+                  const drt_freq_grid *fg, double eps, void *H, void *stream);
+
 /* Serving: enqueue one channel-prediction request.  Non-blocking.  DRT_E_ADMISSION if
  * its device footprint alone exceeds the cap; otherwise it waits in the queue until a
  * batch slot and memory free up.  A worker thread keeps up to four batches in flight, each

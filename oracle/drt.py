@@ -39,6 +39,7 @@ import numpy as np
 from .kinematics import terminal_state, body_poses, place_points, rotate, material_velocity
 from .geometry import dot, norm, mirror, reflection_chain, edge_point, direction_angles
 from .em import fresnel_gamma, utd_coefficient, er_gain
+from . import polar
 
 C0 = 299_792_458.0
 KIND_R, KIND_D, KIND_S = 1, 2, 3
@@ -185,9 +186,13 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
     aod_az, aod_el = direction_angles(khat[0])
     aoa_az, aoa_el = direction_angles(-khat[-1])
 
-    # field coefficient at the carrier
+    # field coefficient at the carrier: the scalar model multiplies the coefficient of each
+    # interaction's polarisation flag; with dipole antennas (polar.py) both coefficients of
+    # every interaction enter the dyadic transport instead
     lam = C0 / f_c
     k = 2.0 * math.pi / lam
+    ants = polar.antennas(scene)
+    coef = [None] * n
     gam = np.ones((Ng, T), dtype=np.complex128)
     for i in range(n):
         if kinds[i] != KIND_R:
@@ -195,9 +200,17 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
         pl = prims[:, i]
         mat = scene["plane_mat"][pl]
         cos_t = np.abs(dot(khat[i], slots[i]["n"]))
-        gam = gam * fresnel_gamma(cos_t, scene["mat_eps_r"][mat][:, None],
-                                  scene["mat_sigma"][mat][:, None], lam,
-                                  scene["mat_pec"][mat][:, None] != 0, pols[:, i][:, None])
+        args = (cos_t, scene["mat_eps_r"][mat][:, None], scene["mat_sigma"][mat][:, None], lam,
+                scene["mat_pec"][mat][:, None] != 0)
+        if ants is None:
+            gam = gam * fresnel_gamma(*args, pols[:, i][:, None])
+        else:
+            coef[i] = (fresnel_gamma(*args, 0), fresnel_gamma(*args, 1), slots[i]["n"])
+    if ants is not None:
+        if KIND_D in kinds:
+            coef[extra["d"]] = "pending"
+        else:
+            gam = polar.transport(ants, kinds, khat, coef)
     if n == 0 or (KIND_D not in kinds and KIND_S not in kinds):
         a = gam * lam / (4.0 * math.pi * L)
     elif KIND_S in kinds:
@@ -213,6 +226,8 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
             a[g] = er_gain(scene["tile_model"][tt], scene["tile_alpha"][tt], scene["tile_S"][tt],
                            scene["tile_area"][tt], scene["tile_phase0"][tt], cos_ti[g],
                            cos_ts[g], cos_psi[g], lens[0][g], lens[1][g], lam)
+        if ants is not None:
+            a = a * gam
         valid &= (cos_ti > 0.0) & (cos_ts > 0.0)
     else:
         d = extra["d"]
@@ -229,7 +244,12 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
         phi = np.mod(np.arctan2(dot(uo, ed["n"]), dot(uo, ed["t"])), 2.0 * math.pi)
         Ld = s * sp * sin_b0 ** 2 / (s + sp)
         wn = scene["edge_wedge_n"][prims[:, d]][:, None]
-        D = utd_coefficient(phi, phi_p, sin_b0, wn, k, Ld, pols[:, d][:, None])
+        if ants is None:
+            D = utd_coefficient(phi, phi_p, sin_b0, wn, k, Ld, pols[:, d][:, None])
+        else:
+            coef[d] = (utd_coefficient(phi, phi_p, sin_b0, wn, k, Ld, 0),
+                       utd_coefficient(phi, phi_p, sin_b0, wn, k, Ld, 1), e)
+            D = polar.transport(ants, kinds, khat, coef)
         a = gam * lam / (4.0 * math.pi) * D / np.sqrt(sp * s * (sp + s))
 
     margin = _bounds_margin(scene, kinds, prims, slots, verts, pts, poses)

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdrt.so")
-SOURCES = ("kernels.hip", "runtime.hip", "trace.hip", "probe.hip")
+SOURCES = ("kernels.hip", "runtime.hip", "trace.hip", "nufft.hip", "probe.hip")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -9,7 +9,7 @@
 
 namespace drt {
 
-enum GeomMode { GEOM_EXTRAP = 0, GEOM_ANCHOR = 1, GEOM_ANCHOR_MFMA = 2, GEOM_KIN = 3, GEOM_POWER = 4 };
+enum GeomMode { GEOM_EXTRAP = 0, GEOM_ANCHOR = 1, GEOM_ANCHOR_MFMA = 2, GEOM_KIN = 3, GEOM_POWER = 4, GEOM_NUFFT = 5 };
 enum CfrPath { CFR_VALU = 0, CFR_MFMA = 1, CFR_MFMA16 = 2 };
 
 constexpr int kNK = 16;          // subcarriers walked by one lane from its phase anchor
@@ -142,6 +142,15 @@ __host__ __device__ inline void trace_decode(const TraceSig& g, int64_t c, int32
     prim[i] = p;
   }
 }
+
+// Non-uniform-FFT ray sum: per (instant, ray), instant-major, binary64: x = frac(df L / c)
+// and c = a exp(-j 2 pi frac(f_c L / c)) (zero for an inconsistent chain).
+struct RecU {
+  double x, cr, ci;
+};
+
+hipError_t launch_nufft(const RecU* rec, int R, int T, int K, int M, int w, double beta, double2* tw,
+                        double* phihat, double2* quad, double2* H, hipStream_t st);
 
 hipError_t launch_trace_cand(const SceneView& sc, const TraceSig& g, int sig_id, uint64_t* keys, uint32_t cap,
                              uint32_t* counter, hipStream_t st);

@@ -209,6 +209,18 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
       const bool in = cnt && u >= 0.0 && u < double(eo.n_delay);
       wave_bin_add(eo.pdp, in ? tb * eo.n_delay + int(u) : -1, p, lane);
     }
+  } else if constexpr (MODE == GEOM_NUFFT) {
+    // non-uniform FFT record: x = frac(df L / c), c = a exp(-j 2 pi frac(f_c L / c)), both
+    // phases reduced modulo one cycle in binary64
+    if (!active) return;
+    const double L = double(res.L);
+    double px = L * ap.f1c, pc = L * ap.f0c;
+    px -= floor(px);
+    pc -= floor(pc);
+    double s, c;
+    sincospi(2.0 * pc, &s, &c);
+    const double gr = double(res.gain.re), gi = double(res.gain.im);
+    reinterpret_cast<RecU*>(rec)[size_t(t) * n_rays + r] = {px, gr * c + gi * s, gi * c - gr * s};
   } else if constexpr (MODE == GEOM_ANCHOR_MFMA) {
     // phases of the first subcarrier, of one row block and of one subcarrier, each reduced
     // modulo one cycle in binary64 before rounding to binary32; the gain enters as its
@@ -898,6 +910,8 @@ static hipError_t launch_geom_mode(const SceneView& sc, const RayClasses& rc, co
                                    const AnchorParams& ap, hipStream_t st) {
   if constexpr (MODE == GEOM_ANCHOR_MFMA) {
     launch_classes<double, MODE, DRT_SPLIT>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
+  } else if constexpr (MODE == GEOM_NUFFT) {
+    launch_classes<double, MODE, DRT_FP64>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
   } else if constexpr (MODE == GEOM_KIN) {
     (void)prec;   // jets in binary64 whatever the call's precision (binary64 pose table)
     launch_classes<double, MODE, DRT_FP64>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
@@ -924,6 +938,8 @@ hipError_t launch_geom(const SceneView& sc, const RayClasses& rc, const void* po
     return launch_geom_mode<GEOM_KIN>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
   if (mode == GEOM_POWER)
     return launch_geom_mode<GEOM_POWER>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
+  if (mode == GEOM_NUFFT)
+    return launch_geom_mode<GEOM_NUFFT>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
   return launch_geom_mode<GEOM_ANCHOR>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
 }
 

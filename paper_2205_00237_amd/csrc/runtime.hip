@@ -1490,6 +1490,53 @@ int drt_cfr(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg,
   return run_cfr(c, *s, n_rays, tg, fg, prec, H, p, sc.buf.p, hs);
 }
 
+int drt_cfr_nufft(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg, const drt_freq_grid* fg,
+                  double eps, void* H, void* stream) {
+  if (!c) return fail(DRT_E_INVAL, "null context");
+  Scene* s = find_scene(c, scene);
+  if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
+  int st;
+  if ((st = check_grid(tg, n_rays, *s)) || (st = check_fgrid(fg))) return st;
+  if (!(eps >= 1e-15 && eps <= 1e-1)) return fail(DRT_E_INVAL, "eps must be in [1e-15, 1e-1]");
+  if (fg->n_sub > 2048) return fail(DRT_E_INVAL, "n_sub %d above 2048", fg->n_sub);
+  const int T = tg->n_steps, K = fg->n_sub;
+  if (T == 0 || K == 0) return DRT_OK;
+  if (!H) return fail(DRT_E_INVAL, "null H");
+  if ((st = set_device(c))) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  if (n_rays == 0) {
+    HIP_OK(launch_zero(H, size_t(T) * K * 16, hs));
+    return DRT_OK;
+  }
+  const int w = std::min(16, std::max(2, int(std::ceil(-std::log10(eps))) + 1));
+  int M = 1;
+  while (M < 2 * K || M < 2 * w) M *= 2;    // a kernel footprint wraps the grid at most once
+  const double beta = 2.30 * w;
+  const size_t pb = (pose_bytes(s->view.n_bodies, T, DRT_FP64) + 255) / 256 * 256;
+  const size_t rb = (size_t(T) * n_rays * sizeof(RecU) + 255) / 256 * 256;
+  const size_t tb = (size_t(M / 2) * 16 + 255) / 256 * 256;
+  std::lock_guard<std::mutex> g(c->scratch_mu);
+  Scratch& sc = c->scratch[hs];
+  const size_t kb = (size_t(K) * 8 + 255) / 256 * 256;
+  if ((st = ensure_scratch(c, sc, pb + rb + tb + kb + 64 * 16, hs))) return st;
+  char* base = (char*)sc.buf.p;
+  HIP_OK(timed(c, DRT_K_POSE, hs, [&] {
+    return launch_pose((const DBody*)s->d_bodies.p, s->view.n_bodies, T, tg->dt, DRT_FP64, base, hs);
+  }));
+  const double inv_c = 1.0 / 299792458.0, df = fg->bandwidth / K;
+  const RayClasses rc = classes(*s, n_rays);
+  ExtrapOut none{};
+  HIP_OK(timed(c, DRT_K_GEOM, hs, [&] {
+    return launch_geom(device_view(*s), rc, base, T, tg->dt, fg->f_c, n_rays, DRT_FP64, GEOM_NUFFT, none, base + pb,
+                       AnchorParams{fg->f_c * inv_c, 0.0, df * inv_c}, hs);
+  }, class_kernels(rc, T)));
+  HIP_OK(timed(c, DRT_K_CFR, hs, [&] {
+    return launch_nufft((const RecU*)(base + pb), n_rays, T, K, M, w, beta, (double2*)(base + pb + rb),
+                        (double*)(base + pb + rb + tb), (double2*)(base + pb + rb + tb + kb), (double2*)H, hs);
+  }, 3));
+  return DRT_OK;
+}
+
 int drt_profile_enable(drt_ctx* c, int on) {
   if (!c) return fail(DRT_E_INVAL, "null context");
   c->prof.store(on != 0);

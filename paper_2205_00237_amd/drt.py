@@ -137,6 +137,16 @@ class Context:
                      out.data_ptr(), _stream(stream))
         return out
 
+    def cfr_nufft(self, sid, tgrid, fgrid, eps=1e-9, n_rays=None, out=None, stream=None):
+        """H(t_j, f_k) [n_steps][n_sub] complex128 by the type-1 non-uniform FFT along f."""
+        R = self.n_rays[sid] if n_rays is None else int(n_rays)
+        T, K = int(tgrid.n_steps), int(fgrid.n_sub)
+        if out is None:
+            out = torch.empty((T, K), dtype=torch.complex128, device=self.device)
+        _abi.drt_cfr_nufft(self.ctx, sid, R, tgrid.dt, T, fgrid.f_c, fgrid.bandwidth, K, eps, out.data_ptr(),
+                           _stream(stream))
+        return out
+
     def submit(self, sid, n_rays, tgrid, fgrid, H, precision=DRT_SPLIT):
         return _abi.drt_submit(self.ctx, sid, n_rays, tgrid.dt, tgrid.n_steps, fgrid.f_c,
                                fgrid.bandwidth, fgrid.n_sub, precision, H.data_ptr())

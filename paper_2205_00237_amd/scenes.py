@@ -509,6 +509,41 @@ class Request:
     n_sub: int
 
 
+def street_canyon(seed=6, n_segments=8, n_vehicles=6, f_c=5.9e9, n_steps=400, dt=2.5e-3):
+    """A street between two rows of building facades (dense multi-bounce traffic for the
+    snapshot tracer): an unbounded ground (eps_r 5, sigma 0.05), facade segments 20 m long
+    along x with 2 m alleys at y = +-10 m (heights U(8, 20) m, normals into the street,
+    eps_r U(3, 7)), each with its two vertical building-corner edges (n = 1.5, 0-face the
+    facade), and box vehicles (4.5 x 1.8 x 1.5 m, PEC) in the lanes y = +-2.5 m driving
+    along x at U(5, 15) m/s.  Tx and Rx at 1.5 m in the street, Tx moving at 10 m/s.  The
+    scene has no rays: trace it."""
+    rng = np.random.default_rng(seed)
+    b = SceneBuilder()
+    ground_mat = b.add_material(5.0, 0.05, False)
+    b.add_plane(0, ground_mat, (0, 0, 0), (0, 0, 1))
+    for side in (1.0, -1.0):
+        n = np.array([0.0, -side, 0.0])
+        for i in range(n_segments):
+            x0, h = 22.0 * i, rng.uniform(8.0, 20.0)
+            mat = b.add_material(rng.uniform(3.0, 7.0), 0.0, False)
+            c = np.array([x0 + 10.0, side * 10.0, 0.5 * h])
+            b.add_plane(0, mat, c, n, facet=((x0, side * 10.0, 0.0), (20.0, 0.0, 0.0), (0.0, 0.0, h)))
+            for xe, t in ((x0, (1.0, 0.0, 0.0)), (x0 + 20.0, (-1.0, 0.0, 0.0))):
+                b.add_edge(0, (xe, side * 10.0, 0.5 * h), (0, 0, 1), t, n, 1.5, zlim=(-0.5 * h, 0.5 * h))
+    pec = b.add_material(1.0, 0.0, True)
+    for _ in range(n_vehicles):
+        lane = 2.5 if rng.random() < 0.5 else -2.5
+        centre = np.array([rng.uniform(10.0, 22.0 * n_segments - 10.0), lane, 1.05])
+        speed = rng.uniform(5.0, 15.0) * (1.0 if lane < 0 else -1.0)
+        body = b.add_body(centre, v0=(speed, 0, 0))
+        add_box(b, body, pec, centre, (4.5, 1.8, 1.5))
+    L = 22.0 * n_segments
+    tx = (rng.uniform(0.2, 0.4) * L, -4.5, 1.5)
+    rx = (rng.uniform(0.6, 0.8) * L, 4.5, 1.5)
+    scene = b.build(tx_p=tx, rx_p=rx, tx_v=(10.0, 0, 0))
+    return scene, TimeGrid(dt, n_steps), FreqGrid(f_c, 240e6, 256)
+
+
 def config5_scenes(n_scenes=64, scale=4):
     """64 resident urban scenes of 20 000 rays (configuration 2's mix times 4)."""
     return [config2(seed=5000 + i, scale=scale)[0] for i in range(n_scenes)]

@@ -23,7 +23,8 @@ def _declared(headers=(HEADER,)):
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ("drt_create", "drt_destroy", "drt_load_scene", "drt_unload_scene", "drt_extrapolate",
-              "drt_cfr", "drt_power_profiles", "drt_trace", "drt_scene_rays", "drt_submit", "drt_poll", "drt_strerror", "drt_last_error", "drt_now"):
+              "drt_cfr", "drt_cfr_nufft", "drt_power_profiles", "drt_trace", "drt_scene_rays",
+              "drt_segments", "drt_submit", "drt_poll", "drt_strerror", "drt_last_error", "drt_now"):
         assert n in names
 
 
@@ -67,7 +68,8 @@ def test_struct_layouts_match_the_header(tmp_path):
              ("drt_request", _abi.Request), ("drt_req_stat", _abi.ReqStat),
              ("drt_profile", _abi.Profile), ("drt_serving_stats", _abi.ServingStats),
              ("drt_bins", _abi.Bins), ("drt_power_out", _abi.PowerOut),
-             ("drt_trace_opts", _abi.TraceOpts), ("drt_trace_info", _abi.TraceInfo)]
+             ("drt_trace_opts", _abi.TraceOpts), ("drt_trace_info", _abi.TraceInfo),
+             ("drt_refresh_opts", _abi.RefreshOpts)]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "drt.h"', "int main(void) {"]
     for cname, cls in pairs:
         lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')

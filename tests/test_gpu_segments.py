@@ -1,7 +1,7 @@
 """Multipath lifetimes on the GPU (Sec. II: trace, extrapolate while no major path
 disappears, trace again) through the C ABI against the oracle: identical segment
-boundaries and traced paths on the sliding-box scene, the moving-box scenes and the urban
-scene, and H over the whole span assembled from the segments' scenes against the oracle's
+boundaries and traced paths on the sliding-box scene, the moving-box scenes, the urban
+scene and a street canyon, and H over the whole span assembled from the segments' scenes against the oracle's
 H of the same segments (binary64: |dH| <= 1e-6 rms; split: the parity bar of the ray sum)."""
 import math
 
@@ -95,6 +95,12 @@ def test_urban(ctx):
     s, tg, fg = scenes.config2()
     opts = dict(max_refl=2, max_refl_diff=1, scattering=False, los=True)
     run_case(ctx, s, tg, fg.f_c, opts, 10.0, 250, "urban", fg=scenes.FreqGrid(fg.f_c, fg.bandwidth, 256))
+
+
+def test_street_canyon(ctx):
+    s, tg, fg = scenes.street_canyon()
+    opts = dict(max_refl=2, max_refl_diff=1, scattering=False, los=True)
+    run_case(ctx, s, tg, fg.f_c, opts, 20.0, 100, "canyon", fg=fg)
 
 
 def test_errors(ctx):

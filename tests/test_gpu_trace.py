@@ -173,6 +173,17 @@ def test_urban(ctx):
     ctx.unload_scene(sid)
 
 
+@pytest.mark.parametrize("t", [0.0, 0.3])
+def test_street_canyon(ctx, t):
+    # dense multi-bounce traffic: up to three reflections, one diffraction with up to two
+    s, _, _ = scenes.street_canyon()
+    new, ref, info = check_trace(ctx, s, t, f"canyon t={t}", max_refl=3, max_refl_diff=2, scattering=False,
+                                 los=True)
+    kinds = [k for k, *_ in ref]
+    assert sum(1 for k in kinds if len(k) == 3) >= 100 and info["n_diff"] >= 100
+    ctx.unload_scene(new)
+
+
 def test_trace_errors(ctx):
     from paper_2205_00237_amd._abi import DrtError
     s, _, _ = scenes.config1()

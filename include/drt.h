@@ -101,6 +101,16 @@ typedef struct {
                                                   NULL: every wall unbounded */
   const double *edge_zlim;                     /* [ne][2] the edge segment z_lo <= (X - a0) . e0 <= z_hi
                                                   (infinities allowed); NULL: every edge unbounded */
+  /* Antennas (optional, both or neither): [4] = unit axis (x, y, z) and kind, 1 = half-wave
+   * dipole along the axis (directivity 1.64; the antennas of Sec. IV-B).  With dipoles the
+   * field coefficients are polarimetric: the transmitted vector pattern is carried through
+   * every reflection (Fresnel perpendicular and parallel coefficients on the basis
+   * e_perp = k_in x n, e_par = e_perp x k) and diffraction (UTD soft coefficient for the
+   * component along e_beta = s x (e x s)/|e x s|, hard for the one along (e x s)/|e x s|), a
+   * tile keeps the field, and the result is projected on the received pattern; the rays'
+   * polarisation flags are then ignored.  Needs DRT_FP64 or DRT_SPLIT.  NULL, or kind 0 for
+   * both: the scalar model with the flags. */
+  const double *tx_ant, *rx_ant;
 } drt_scene_desc;
 
 /* t_j = t0 + j*dt, j = 0..n_steps-1. */

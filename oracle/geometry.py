@@ -82,3 +82,52 @@ def edge_point(A, B, a, e):
 def direction_angles(v):
     """Azimuth atan2(y, x) in (-pi, pi] and elevation atan2(z, hypot(x, y)) of v (...,3)."""
     return np.arctan2(v[..., 1], v[..., 0]), np.arctan2(v[..., 2], np.hypot(v[..., 0], v[..., 1]))
+
+
+def double_edge_points(A, B, a1, e1, a2, e2, iters=60):
+    """Points Q1 = a1 + z1 e1 and Q2 = a2 + z2 e2 of the path A -> Q1 -> Q2 -> B over two
+    edges (the multiple-diffraction extension of Sec. III-B): the stationary, here shortest,
+    length |Q1 - A| + |Q2 - Q1| + |B - Q2| (Fermat; Keller's law at both edges), a convex
+    function of (z1, z2).  Newton's method with step halving from the single-edge points.
+
+    Returns (Q1, Q2, z1, z2, converged) broadcast over the leading dims."""
+    def length(z1, z2):
+        Q1 = a1 + z1[..., None] * e1
+        Q2 = a2 + z2[..., None] * e2
+        return norm(Q1 - A) + norm(Q2 - Q1) + norm(B - Q2)
+
+    z1 = edge_point(A, B, a1, e1)[0]
+    z2 = edge_point(A, B, a2, e2)[0]
+    z1 = dot(z1 - a1, e1)
+    z2 = dot(z2 - a2, e2)
+    f = length(z1, z2)
+    g1 = g2 = np.ones_like(z1)
+    for _ in range(iters):
+        Q1 = a1 + z1[..., None] * e1
+        Q2 = a2 + z2[..., None] * e2
+        d0, d1, d2 = Q1 - A, Q2 - Q1, B - Q2
+        l0, l1, l2 = norm(d0), norm(d1), norm(d2)
+        c0, c1a, c1b, c2 = dot(d0, e1) / l0, dot(d1, e1) / l1, dot(d1, e2) / l1, dot(d2, e2) / l2
+        g1 = c0 - c1a
+        g2 = c1b - c2
+        h11 = (1.0 - c0 * c0) / l0 + (1.0 - c1a * c1a) / l1
+        h22 = (1.0 - c1b * c1b) / l1 + (1.0 - c2 * c2) / l2
+        h12 = -(dot(e1, e2) - c1a * c1b) / l1
+        det = h11 * h22 - h12 * h12
+        with np.errstate(divide="ignore", invalid="ignore"):
+            s1 = -(h22 * g1 - h12 * g2) / det
+            s2 = -(h11 * g2 - h12 * g1) / det
+        s1 = np.where(np.isfinite(s1), s1, -g1)
+        s2 = np.where(np.isfinite(s2), s2, -g2)
+        lam = np.ones_like(z1)
+        for _ in range(40):          # halve until the length does not increase
+            fn = length(z1 + lam * s1, z2 + lam * s2)
+            bad = fn > f
+            if not bad.any():
+                break
+            lam = np.where(bad, 0.5 * lam, lam)
+        z1, z2, f = z1 + lam * s1, z2 + lam * s2, length(z1 + lam * s1, z2 + lam * s2)
+    Q1 = a1 + z1[..., None] * e1
+    Q2 = a2 + z2[..., None] * e2
+    conv = (np.abs(g1) < 1e-9) & (np.abs(g2) < 1e-9)
+    return Q1, Q2, z1, z2, conv

@@ -58,6 +58,7 @@ class SceneDesc(C.Structure):
         ("ray_nint", _u8p), ("ray_kind", _u8p), ("ray_pol", _u8p), ("ray_prim", _i32p),
         ("ray_q0", _dp),
         ("plane_facet", _dp), ("edge_zlim", _dp),
+        ("tx_ant", _dp), ("rx_ant", _dp),
     ]
 
 
@@ -237,6 +238,11 @@ def scene_desc(scene, ray_q0=None):
         z = _arr(scene["edge_zlim"], np.float64, (d.n_edges, 2))
         keep["edge_zlim"] = z
         d.edge_zlim = z.ctypes.data_as(_dp)
+    for k in ("tx_ant", "rx_ant"):        # the library checks that both or neither are given
+        if k in scene:
+            a = _arr(scene[k], np.float64, (4,))
+            keep[k] = a
+            setattr(d, k, a.ctypes.data_as(_dp))
     return d, keep
 
 

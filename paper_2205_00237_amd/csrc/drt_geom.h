@@ -438,6 +438,56 @@ template <class F> DRT_HD void dir_angles(V3<F> v, F& az, F& el) {
   el = matan2(v.z, msqrt(v.x * v.x + v.y * v.y));
 }
 
+// ---------------------------------------------------------------------------------------
+// polarimetric coefficients with half-wave dipoles (vector form of the interactions)
+
+template <class G> struct CV3 { Cx<G> x, y, z; };
+template <class G> DRT_HD CV3<G> cv3(Cx<G> s, V3<G> v) { return {v.x * s, v.y * s, v.z * s}; }
+template <class G> DRT_HD CV3<G> operator+(CV3<G> a, CV3<G> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class G> DRT_HD Cx<G> cdot(CV3<G> a, V3<G> v) { return v.x * a.x + v.y * a.y + v.z * a.z; }
+template <class G> DRT_HD V3<G> unit_or(V3<G> v, V3<G> alt) {
+  const G n2 = dot(v, v);
+  if (!(n2 > G(1e-24))) { v = alt; }
+  return frcp(norm(v)) * v;
+}
+
+// Vector pattern of a half-wave dipole along the unit p towards the unit direction k:
+// sqrt(1.64) cos((pi/2) cos theta) / sin theta times theta_hat = ((p.k) k - p) / sin theta,
+// evaluated as sin((pi/2) s^2 / (1 + |c|)) / s^2 times (c k - p) (no cancellation near the
+// axis, where it vanishes with s).
+template <class G> DRT_HD V3<G> dipole_pattern(V3<G> p, V3<G> k) {
+  const G c = dot(p, k);
+  const V3<G> t = c * k - p;
+  const G s2 = dot(t, t), ac = c < G(0) ? -c : c;
+  const G x = s2 * frcp(G(1) + ac);
+  G amp = Consts<G>::pi * G(0.5) * frcp(G(1) + ac);
+  if (s2 > G(0)) {
+    G sn, cs;
+    sincos_small(Consts<G>::pi * G(0.5) * x, sn, cs);
+    amp = sn * frcp(s2);
+  }
+  return (G(1.2806248474865698) * amp) * t;     // sqrt(1.64)
+}
+
+// Reflection dyadic: e_perp = k_in x n normalised, e_par = e_perp x k on each side;
+// E -> G_perp (E.e_perp) e_perp + G_par (E.e_par_in) e_par_out.
+template <class G>
+DRT_HD CV3<G> reflect_field(CV3<G> E, V3<G> k_in, V3<G> k_out, V3<G> n, Cx<G> g_perp, Cx<G> g_par) {
+  const G az = n.z < G(0) ? -n.z : n.z;
+  const V3<G> alt = cross(n, az < G(0.9) ? V3<G>{G(0), G(0), G(1)} : V3<G>{G(1), G(0), G(0)});
+  const V3<G> ep = unit_or(cross(k_in, n), alt);
+  return cv3(g_perp * cdot(E, ep), ep) + cv3(g_par * cdot(E, cross(ep, k_in)), cross(ep, k_out));
+}
+
+// UTD dyadic: e_phi = e x s normalised, e_beta = s x e_phi on each side;
+// E -> D_s (E.e_beta_in) e_beta_out + D_h (E.e_phi_in) e_phi_out.
+template <class G>
+DRT_HD CV3<G> diffract_field(CV3<G> E, V3<G> s_in, V3<G> s_out, V3<G> e, Cx<G> d_soft, Cx<G> d_hard) {
+  const V3<G> pi_ = unit_or(cross(e, s_in), cross(e, V3<G>{G(1), G(0), G(0)}));
+  const V3<G> po = unit_or(cross(e, s_out), cross(e, V3<G>{G(1), G(0), G(0)}));
+  return cv3(d_soft * cdot(E, cross(s_in, pi_)), cross(s_out, po)) + cv3(d_hard * cdot(E, pi_), po);
+}
+
 // Evaluate one ray whose N interaction slots are already moved to the instant.  Geometry
 // (points, length, Doppler) is computed in F; angles and the field coefficient in G.
 // Template parameters fix the signature so that every array stays in registers; the
@@ -446,7 +496,7 @@ template <class F> DRT_HD void dir_angles(V3<F> v, F& az, F& el) {
 // the validity monitor is evaluated too: every reflection point inside its wall's facet
 // (tested in the wall body's t0 frame, where the facet is fixed) with both neighbouring
 // vertices on the front side, and every diffraction point on its edge segment.
-template <class F, class G, int N, int DP, bool SCAT, bool KEEP_Q = false, bool MON = false>
+template <class F, class G, int N, int DP, bool SCAT, bool KEEP_Q = false, bool MON = false, bool POL = false>
 DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot<F>* sl, V3<F> TX,
                                 V3<F> VTX, V3<F> RX, V3<F> VRX, F f_c) {
   RayResult<F, G> res;
@@ -493,13 +543,32 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
   const G pi = Consts<G>::pi;
   const G lam = G(Consts<F>::c0 / f_c);
   Cx<G> gam = cx<G>(G(1), G(0));
+  // with dipoles: the transmitted pattern, carried through the reflections here (and the
+  // diffraction below), is projected on the received pattern into gam
+  CV3<G> E{};
+  if constexpr (POL) {
+    const V3<G> pt{G(sc.tx_ant[0]), G(sc.tx_ant[1]), G(sc.tx_ant[2])};
+    const V3<G> e0 = dipole_pattern(pt, gv(kh[0]));
+    E = CV3<G>{cx<G>(e0.x, G(0)), cx<G>(e0.y, G(0)), cx<G>(e0.z, G(0))};
+  }
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     if (SCAT || i == DP) continue;
     const DPlane& pl = sc.planes[ray.prim[i]];
     G ct = G(mfabs(dot(dv[i], sl[i].n))) * frcp(G(len[i]));
-    gam = gam * fresnel<G>(ct, sc.mats[pl.mat], lam, ray.pol[i]);
+    if constexpr (POL) {
+      if (DP >= 0 && i > DP) continue;     // after the edge: applied with the diffraction
+      E = reflect_field(E, gv(kh[i]), gv(kh[i + 1]), gv(sl[i].n), fresnel<G>(ct, sc.mats[pl.mat], lam, DRT_PERP),
+                        fresnel<G>(ct, sc.mats[pl.mat], lam, DRT_PAR));
+    } else {
+      gam = gam * fresnel<G>(ct, sc.mats[pl.mat], lam, ray.pol[i]);
+    }
   }
+  auto receive = [&](CV3<G> Ef) {
+    const V3<G> pr{G(sc.rx_ant[0]), G(sc.rx_ant[1]), G(sc.rx_ant[2])};
+    return cdot(Ef, dipole_pattern(pr, gv(-kh[N])));
+  };
+  if constexpr (POL && DP < 0) gam = receive(E);
   bool ok = ch.ok;
   Cx<G> a;
   if constexpr (SCAT) {
@@ -526,6 +595,7 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
     G sp_, cp_;
     sincos_small(ph, sp_, cp_);     // tile phase in [0, 2 pi)
     a = cx<G>(sc_ * cp_, sc_ * sp_);
+    if constexpr (POL) a = a * gam;   // the tile keeps the field: the two patterns' projection
   } else if constexpr (DP >= 0) {
     const DEdge& ed = sc.edges[ray.prim[DP]];
     const Slot<F>& es = sl[DP];
@@ -544,9 +614,23 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
     if (phi < F(0)) phi += F(2) * piF;
     G Ld = G(s * sp * sb * sb) * frcp(G(s + sp));
     G k = G(2) * pi / lam;
-    Cx<G> D = utd_coefficient<F, G>(phi, phi_p, G(sb), F(ed.wn), k, Ld, ray.pol[DP]);
     G scale = lam / (G(4) * pi) * frcp(msqrt(G(sp * s * (sp + s))));
-    a = scale * (gam * D);
+    if constexpr (POL) {
+      E = diffract_field(E, gv(kh[DP]), gv(kh[DP + 1]), gv(es.e),
+                         utd_coefficient<F, G>(phi, phi_p, G(sb), F(ed.wn), k, Ld, DRT_PERP),
+                         utd_coefficient<F, G>(phi, phi_p, G(sb), F(ed.wn), k, Ld, DRT_PAR));
+#pragma unroll
+      for (int i = DP + 1; i < N; ++i) {
+        const DPlane& pl = sc.planes[ray.prim[i]];
+        G ct = G(mfabs(dot(dv[i], sl[i].n))) * frcp(G(len[i]));
+        E = reflect_field(E, gv(kh[i]), gv(kh[i + 1]), gv(sl[i].n),
+                          fresnel<G>(ct, sc.mats[pl.mat], lam, DRT_PERP), fresnel<G>(ct, sc.mats[pl.mat], lam, DRT_PAR));
+      }
+      a = scale * receive(E);
+    } else {
+      Cx<G> D = utd_coefficient<F, G>(phi, phi_p, G(sb), F(ed.wn), k, Ld, ray.pol[DP]);
+      a = scale * (gam * D);
+    }
   } else {
     a = (lam * frcp(G(4) * pi * G(L))) * gam;
   }

@@ -73,7 +73,9 @@ struct SceneView {
   const DRay* rays;
   double tx_p[3], tx_v[3], tx_a[3];
   double rx_p[3], rx_v[3], rx_a[3];
+  double tx_ant[3], rx_ant[3];   // dipole axes (polar = 1)
   int32_t n_bodies, n_rays;
+  int32_t polar, pad_;
 };
 
 }  // namespace drt

@@ -77,7 +77,7 @@ __device__ __forceinline__ void wave_bin_add(double* base, int key, double v, in
 }
 
 // One wave: ray order[i] over the 64 instants of chunk c, where wave = 4 (nchunk (i / 4) + c) + i % 4.
-template <class F, int MODE, int PREC, int CLS>
+template <class F, int MODE, int PREC, int CLS, bool POL = false>
 __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* order, int count,
                                           const typename Vec2<F>::type* pose, int T, double dt, double f_c,
                                           int n_rays, int nchunk, const ExtrapOut& eo, void* rec,
@@ -165,8 +165,8 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   F fc = F(f_c);
   using G = typename GainT<PREC>::type;
   RayResult<F, G> res = with_signature_in<F, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
-    return eval_ray<F, G, N, DP, SCAT, false, MODE == GEOM_EXTRAP || MODE == GEOM_POWER>(sc, ray, sl, TX, VTX,
-                                                                                         RX, VRX, fc);
+    return eval_ray<F, G, N, DP, SCAT, false, MODE == GEOM_EXTRAP || MODE == GEOM_POWER, POL>(sc, ray, sl, TX,
+                                                                                              VTX, RX, VRX, fc);
   });
 
   if constexpr (MODE == GEOM_EXTRAP) {
@@ -265,13 +265,13 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   }
 }
 
-template <class F, int MODE, int PREC, int CLS>
+template <class F, int MODE, int PREC, int CLS, bool POL>
 __global__ __launch_bounds__(256) void k_geom(SceneView sc, const int32_t* order, int count,
                                               const typename Vec2<F>::type* pose, int T, double dt, double f_c,
                                               int n_rays, int nchunk, ExtrapOut eo, void* rec, AnchorParams ap) {
   int wave = __builtin_amdgcn_readfirstlane(int(blockIdx.x) * 4 + int(threadIdx.x >> 6));
-  geom_wave<F, MODE, PREC, CLS>(sc, order, count, pose, T, dt, f_c, n_rays, nchunk, eo, rec, ap, wave,
-                                int(threadIdx.x & 63));
+  geom_wave<F, MODE, PREC, CLS, POL>(sc, order, count, pose, T, dt, f_c, n_rays, nchunk, eo, rec, ap, wave,
+                                     int(threadIdx.x & 63));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -883,7 +883,7 @@ size_t record_bytes(int n_rays, int T, int prec) {
   return size_t((T + 63) / 64) * n_rays * 64 * per;
 }
 
-template <class F, int MODE, int PREC>
+template <class F, int MODE, int PREC, bool POL>
 static void launch_classes(const SceneView& sc, const RayClasses& rc, const void* pose, int T, double dt,
                            double f_c, int n_rays, const ExtrapOut& eo, void* rec, const AnchorParams& ap,
                            hipStream_t st) {
@@ -893,14 +893,37 @@ static void launch_classes(const SceneView& sc, const RayClasses& rc, const void
     if (rc.count[c] == 0) continue;
     dim3 grid(unsigned(long((rc.count[c] + 3) / 4) * nchunk));   // 4 rays x 64 instants per workgroup
     if (c == CLS_R)
-      hipLaunchKernelGGL((k_geom<F, MODE, PREC, CLS_R>), grid, dim3(256), 0, st, sc, rc.order[c], rc.count[c],
+      hipLaunchKernelGGL((k_geom<F, MODE, PREC, CLS_R, POL>), grid, dim3(256), 0, st, sc, rc.order[c], rc.count[c],
                          (P)pose, T, dt, f_c, n_rays, nchunk, eo, rec, ap);
     else if (c == CLS_D)
-      hipLaunchKernelGGL((k_geom<F, MODE, PREC, CLS_D>), grid, dim3(256), 0, st, sc, rc.order[c], rc.count[c],
+      hipLaunchKernelGGL((k_geom<F, MODE, PREC, CLS_D, POL>), grid, dim3(256), 0, st, sc, rc.order[c], rc.count[c],
                          (P)pose, T, dt, f_c, n_rays, nchunk, eo, rec, ap);
     else
-      hipLaunchKernelGGL((k_geom<F, MODE, PREC, CLS_S>), grid, dim3(256), 0, st, sc, rc.order[c], rc.count[c],
+      hipLaunchKernelGGL((k_geom<F, MODE, PREC, CLS_S, POL>), grid, dim3(256), 0, st, sc, rc.order[c], rc.count[c],
                          (P)pose, T, dt, f_c, n_rays, nchunk, eo, rec, ap);
+  }
+}
+
+// The precision instances of one mode; POL: polarimetric field coefficients (dipoles),
+// available in binary64 and split precision.
+template <int MODE, bool POL>
+static void launch_geom_prec(const SceneView& sc, const RayClasses& rc, const void* pose, int T, double dt,
+                             double f_c, int n_rays, int prec, const ExtrapOut& eo, void* rec,
+                             const AnchorParams& ap, hipStream_t st) {
+  if constexpr (MODE == GEOM_ANCHOR_MFMA) {
+    launch_classes<double, MODE, DRT_SPLIT, POL>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
+  } else if constexpr (MODE == GEOM_NUFFT) {
+    launch_classes<double, MODE, DRT_FP64, POL>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
+  } else if constexpr (MODE == GEOM_KIN) {
+    (void)prec;   // jets in binary64 whatever the call's precision (binary64 pose table); no field
+    launch_classes<double, MODE, DRT_FP64, false>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
+  } else {
+    if (prec == DRT_FP64)
+      launch_classes<double, MODE, DRT_FP64, POL>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
+    else if (prec == DRT_SPLIT)
+      launch_classes<double, MODE, DRT_SPLIT, POL>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
+    else if constexpr (!POL)
+      launch_classes<float, MODE, DRT_NAIVE32, false>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
   }
 }
 
@@ -908,20 +931,11 @@ template <int MODE>
 static hipError_t launch_geom_mode(const SceneView& sc, const RayClasses& rc, const void* pose, int T, double dt,
                                    double f_c, int n_rays, int prec, const ExtrapOut& eo, void* rec,
                                    const AnchorParams& ap, hipStream_t st) {
-  if constexpr (MODE == GEOM_ANCHOR_MFMA) {
-    launch_classes<double, MODE, DRT_SPLIT>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
-  } else if constexpr (MODE == GEOM_NUFFT) {
-    launch_classes<double, MODE, DRT_FP64>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
-  } else if constexpr (MODE == GEOM_KIN) {
-    (void)prec;   // jets in binary64 whatever the call's precision (binary64 pose table)
-    launch_classes<double, MODE, DRT_FP64>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
+  if (sc.polar && MODE != GEOM_KIN) {
+    if (prec == DRT_NAIVE32 && MODE != GEOM_ANCHOR_MFMA && MODE != GEOM_NUFFT) return hipErrorInvalidValue;
+    launch_geom_prec<MODE, true>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
   } else {
-    if (prec == DRT_FP64)
-      launch_classes<double, MODE, DRT_FP64>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
-    else if (prec == DRT_SPLIT)
-      launch_classes<double, MODE, DRT_SPLIT>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
-    else
-      launch_classes<float, MODE, DRT_NAIVE32>(sc, rc, pose, T, dt, f_c, n_rays, eo, rec, ap, st);
+    launch_geom_prec<MODE, false>(sc, rc, pose, T, dt, f_c, n_rays, prec, eo, rec, ap, st);
   }
   return hipGetLastError();
 }

@@ -78,6 +78,7 @@ struct HostDesc {
   std::vector<double> tile_c0, tile_n0, tile_area, tile_S, tile_phase0;
   std::vector<uint8_t> ray_nint, ray_kind, ray_pol;
   std::vector<int32_t> ray_prim;
+  std::vector<double> tx_ant, rx_ant;                    // [4] each, or empty
 };
 
 struct Scene {
@@ -379,6 +380,18 @@ static int validate_and_pack(const drt_scene_desc* d, Scene& s) {
   std::memcpy(hv.tx_p, d->tx_p, 24);
   std::memcpy(hv.rx_p, d->rx_p, 24);
   std::memcpy(hv.tx_v, d->tx_v, 24);
+  if ((d->tx_ant == nullptr) != (d->rx_ant == nullptr))
+    return fail(DRT_E_INVAL, "give both antennas or neither");
+  if (d->tx_ant) {
+    const double kt = d->tx_ant[3], kr = d->rx_ant[3];
+    if (!((kt == 0 || kt == 1) && kt == kr)) return fail(DRT_E_INVAL, "antenna kinds must both be 0 or both be 1");
+    if (kt == 1) {
+      if (!unit(d->tx_ant) || !unit(d->rx_ant)) return fail(DRT_E_INVAL, "dipole axes must be unit vectors");
+      std::memcpy(hv.tx_ant, d->tx_ant, 24);
+      std::memcpy(hv.rx_ant, d->rx_ant, 24);
+      hv.polar = 1;
+    }
+  }
   std::memcpy(hv.rx_v, d->rx_v, 24);
   for (int r = 0; r < d->n_rays; ++r) {
     const DRay& R = s.rays[r];
@@ -540,9 +553,11 @@ static int check_fgrid(const drt_freq_grid* fg) {
   return DRT_OK;
 }
 
-static int check_prec(int prec) {
+static int check_prec(int prec, const Scene* s = nullptr) {
   if (prec != DRT_FP64 && prec != DRT_SPLIT && prec != DRT_NAIVE32)
     return fail(DRT_E_INVAL, "unknown precision %d", prec);
+  if (s && s->view.polar && prec == DRT_NAIVE32)
+    return fail(DRT_E_INVAL, "dipole antennas need DRT_FP64 or DRT_SPLIT");
   return DRT_OK;
 }
 
@@ -659,7 +674,7 @@ static void finish(drt_ctx* c, Slot_& sl, int state) {
 
 // A request runs in a graph batch when its ray sum is the binary16 matrix-core one.
 static bool batchable(drt_ctx* c, const Request* q, CfrPlan* p) {
-  if (q->r.precision != DRT_SPLIT) return false;
+  if (q->r.precision != DRT_SPLIT || q->scene->view.polar) return false;   // batch kernels: scalar model
   *p = plan(c, *q->scene, q->r.n_rays, q->r.tg.n_steps, &q->r.fg, q->r.precision);
   return p->a.path == CFR_MFMA16 && cfr_shape(p->a.MT, p->a.NT) >= 0;
 }
@@ -926,6 +941,8 @@ static HostDesc copy_desc(const drt_scene_desc* d) {
   h.ray_kind = vcopy(d->ray_kind, 4 * nr);
   h.ray_pol = vcopy(d->ray_pol, 4 * nr);
   h.ray_prim = vcopy(d->ray_prim, 4 * nr);
+  h.tx_ant = vcopy(d->tx_ant, 4);
+  h.rx_ant = vcopy(d->rx_ant, 4);
   return h;
 }
 
@@ -978,6 +995,8 @@ static drt_scene_desc desc_view(const HostDesc& h) {
   d.ray_pol = ptr_or_null(h.ray_pol);
   d.ray_prim = ptr_or_null(h.ray_prim);
   d.ray_q0 = nullptr;
+  d.tx_ant = ptr_or_null(h.tx_ant);
+  d.rx_ant = ptr_or_null(h.rx_ant);
   return d;
 }
 
@@ -1362,7 +1381,7 @@ int drt_extrapolate(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_g
   Scene* s = find_scene(c, scene);
   if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
   int st;
-  if ((st = check_grid(tg, n_rays, *s)) || (st = check_prec(prec))) return st;
+  if ((st = check_grid(tg, n_rays, *s)) || (st = check_prec(prec, s))) return st;
   if (!(f_c > 0)) return fail(DRT_E_INVAL, "carrier must be > 0");
   if ((st = set_device(c))) return st;
   int T = tg->n_steps;
@@ -1419,7 +1438,7 @@ int drt_power_profiles(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_tim
   Scene* s = find_scene(c, scene);
   if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
   int st;
-  if ((st = check_grid(tg, n_rays, *s)) || (st = check_prec(prec))) return st;
+  if ((st = check_grid(tg, n_rays, *s)) || (st = check_prec(prec, s))) return st;
   if (!(f_c > 0)) return fail(DRT_E_INVAL, "carrier must be > 0");
   if (bins->steps_per_bin < 1) return fail(DRT_E_INVAL, "steps_per_bin must be >= 1");
   if (!(bins->dop_step > 0) || !(bins->delay_step > 0) || !std::isfinite(bins->dop_lo) ||
@@ -1473,7 +1492,7 @@ int drt_cfr(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg,
   Scene* s = find_scene(c, scene);
   if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
   int st;
-  if ((st = check_grid(tg, n_rays, *s)) || (st = check_fgrid(fg)) || (st = check_prec(prec))) return st;
+  if ((st = check_grid(tg, n_rays, *s)) || (st = check_fgrid(fg)) || (st = check_prec(prec, s))) return st;
   if (tg->n_steps > 0 && fg->n_sub > 0 && !H) return fail(DRT_E_INVAL, "null H");
   if ((st = set_device(c))) return st;
   int T = tg->n_steps, K = fg->n_sub;

@@ -37,7 +37,8 @@ import math
 import numpy as np
 
 from .kinematics import terminal_state, body_poses, place_points, rotate, material_velocity
-from .geometry import dot, norm, mirror, reflection_chain, edge_point, direction_angles
+from .geometry import (dot, norm, mirror, reflection_chain, edge_point, double_edge_points,
+                       direction_angles)
 from .em import fresnel_gamma, utd_coefficient, er_gain
 from . import polar
 
@@ -139,6 +140,20 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
         pts = []
     elif kinds == (KIND_S,):
         pts = [slots[0]["c"]]
+    elif kinds == (KIND_D, KIND_D):
+        # two edges: the coupled stationary-length solve (geometry.double_edge_points)
+        e1, e2 = slots[0], slots[1]
+        Q1, Q2, _, _, conv = double_edge_points(TXg, RXg, e1["a"], e1["e"], e2["a"], e2["e"])
+        pts = [Q1, Q2]
+
+        def rho(X, ed):
+            w = X - ed["a"]
+            return norm(w - dot(w, ed["e"])[..., None] * ed["e"])
+        far = ((rho(TXg, e1) > RHO_MIN) & (rho(Q2, e1) > RHO_MIN) & (rho(Q1, e2) > RHO_MIN)
+               & (rho(RXg, e2) > RHO_MIN))
+        valid &= conv & far
+        degen = ~far
+        extra = {"dd": True}
     elif KIND_D in kinds:
         d = kinds.index(KIND_D)
         before = [(slots[i]["p"], slots[i]["n"]) for i in range(d)]
@@ -207,9 +222,7 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
         else:
             coef[i] = (fresnel_gamma(*args, 0), fresnel_gamma(*args, 1), slots[i]["n"])
     if ants is not None:
-        if KIND_D in kinds:
-            coef[extra["d"]] = "pending"
-        else:
+        if KIND_D not in kinds:
             gam = polar.transport(ants, kinds, khat, coef)
     if n == 0 or (KIND_D not in kinds and KIND_S not in kinds):
         a = gam * lam / (4.0 * math.pi * L)
@@ -229,6 +242,34 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
         if ants is not None:
             a = a * gam
         valid &= (cos_ti > 0.0) & (cos_ts > 0.0)
+    elif "dd" in extra:
+        # UTD for successive edges, non-slope: the field diffracted by the first edge reaches
+        # the second as from a source at the unfolded distance s0 + s1 (exact for parallel
+        # edges), so D1 uses L1 = s0 s1 sin^2 b1 / (s0 + s1), D2 uses
+        # L2 = (s0 + s1) s2 sin^2 b2 / (s0 + s1 + s2), and the spreading is
+        # 1 / sqrt(s0 s1 s2 (s0 + s1 + s2))
+        s0, s1, s2 = lens
+        Ds, Ls = [], [s0 * s1 / (s0 + s1), (s0 + s1) * s2 / (s0 + s1 + s2)]
+        for j in range(2):
+            ed = slots[j]
+            e = ed["e"]
+            prev, nxt = verts[j], verts[j + 2]
+            Q = pts[j]
+            cos_b0 = dot(_unit(Q - prev), e)
+            sin_b0 = np.sqrt(np.maximum(1.0 - cos_b0 * cos_b0, 0.0))
+            up = (prev - Q) - dot(prev - Q, e)[..., None] * e
+            uo = (nxt - Q) - dot(nxt - Q, e)[..., None] * e
+            phi_p = np.mod(np.arctan2(dot(up, ed["n"]), dot(up, ed["t"])), 2.0 * math.pi)
+            phi = np.mod(np.arctan2(dot(uo, ed["n"]), dot(uo, ed["t"])), 2.0 * math.pi)
+            wn = scene["edge_wedge_n"][prims[:, j]][:, None]
+            Ld = Ls[j] * sin_b0 ** 2
+            if ants is None:
+                Ds.append(utd_coefficient(phi, phi_p, sin_b0, wn, k, Ld, pols[:, j][:, None]))
+            else:
+                coef[j] = (utd_coefficient(phi, phi_p, sin_b0, wn, k, Ld, 0),
+                           utd_coefficient(phi, phi_p, sin_b0, wn, k, Ld, 1), e)
+        D = Ds[0] * Ds[1] if ants is None else polar.transport(ants, kinds, khat, coef)
+        a = lam / (4.0 * math.pi) * D / np.sqrt(s0 * s1 * s2 * (s0 + s1 + s2))
     else:
         d = extra["d"]
         ed = slots[d]

@@ -120,14 +120,14 @@ def double_edge_points(A, B, a1, e1, a2, e2, iters=60):
         s1 = np.where(np.isfinite(s1), s1, -g1)
         s2 = np.where(np.isfinite(s2), s2, -g2)
         lam = np.ones_like(z1)
-        for _ in range(40):          # halve until the length does not increase
+        for _ in range(40):          # halve while the length increases beyond its rounding
             fn = length(z1 + lam * s1, z2 + lam * s2)
-            bad = fn > f
+            bad = fn > f * (1.0 + 1e-12)
             if not bad.any():
                 break
             lam = np.where(bad, 0.5 * lam, lam)
         z1, z2, f = z1 + lam * s1, z2 + lam * s2, length(z1 + lam * s1, z2 + lam * s2)
     Q1 = a1 + z1[..., None] * e1
     Q2 = a2 + z2[..., None] * e2
-    conv = (np.abs(g1) < 1e-9) & (np.abs(g2) < 1e-9)
+    conv = (np.abs(g1) < 1e-12) & (np.abs(g2) < 1e-12)
     return Q1, Q2, z1, z2, conv

@@ -14,7 +14,8 @@ derivatives are exact up to rounding:
   + R_theta theta'' with R_theta = cos(theta) K + sin(theta) K^2 and
   R_thetatheta = -sin(theta) K + cos(theta) K^2;
 * carried points O + R (X0 - O0) and directions R d0;
-* images, back-tracked reflection points, the edge point and the segment lengths.
+* images, back-tracked reflection points, the edge point and the segment lengths;
+* the two points of a two-edge chain by Newton steps in triple arithmetic.
 
 The Doppler rate is -(f_c / c) d^2 L / dt^2.
 """
@@ -23,6 +24,7 @@ import math
 import numpy as np
 
 from .kinematics import _skew
+from .geometry import double_edge_points
 
 C0 = 299_792_458.0
 KIND_R, KIND_D, KIND_S = 1, 2, 3
@@ -166,6 +168,32 @@ def _edge_point(A, B, a, e):
     return t_add(a, t_scale(zQ, e))
 
 
+def _double_edge(A, B, a1, e1, a2, e2, steps=6):
+    """The two-edge points as triples: the values from geometry.double_edge_points, then
+    Newton steps on the stationarity conditions in triple arithmetic, which carry the first
+    and second time derivatives of (z1, z2) to convergence (the conditions hold at every
+    instant, so their jets vanish)."""
+    _, _, z1v, z2v, _ = double_edge_points(A[0], B[0], a1[0], e1[0], a2[0], e2[0])
+    z1, z2 = t_const(z1v), t_const(z2v)
+    one = t_const(np.ones_like(z1v))
+    for _ in range(steps):
+        Q1 = t_add(a1, t_scale(z1, e1))
+        Q2 = t_add(a2, t_scale(z2, e2))
+        d0, d1, d2 = t_sub(Q1, A), t_sub(Q2, Q1), t_sub(B, Q2)
+        l0, l1, l2 = t_norm(d0), t_norm(d1), t_norm(d2)
+        c0, c1a = t_div(t_dot(d0, e1), l0), t_div(t_dot(d1, e1), l1)
+        c1b, c2 = t_div(t_dot(d1, e2), l1), t_div(t_dot(d2, e2), l2)
+        g1, g2 = t_sub(c0, c1a), t_sub(c1b, c2)
+        h11 = t_add(t_div(t_sub(one, t_mul(c0, c0)), l0), t_div(t_sub(one, t_mul(c1a, c1a)), l1))
+        h22 = t_add(t_div(t_sub(one, t_mul(c1b, c1b)), l1), t_div(t_sub(one, t_mul(c2, c2)), l2))
+        h12 = t_div(t_sub(t_mul(c1a, c1b), t_dot(e1, e2)), l1)
+        det = t_sub(t_mul(h11, h22), t_mul(h12, h12))
+        s1 = t_div(t_sub(t_mul(h12, g2), t_mul(h22, g1)), det)
+        s2 = t_div(t_sub(t_mul(h12, g1), t_mul(h11, g2)), det)
+        z1, z2 = t_add(z1, s1), t_add(z2, s2)
+    return t_add(a1, t_scale(z1, e1)), t_add(a2, t_scale(z2, e2))
+
+
 def _group(scene, rays, kinds, TX, RX, O, R):
     n = len(kinds)
     Ng, T = len(rays), TX[0].shape[0]
@@ -196,6 +224,8 @@ def _group(scene, rays, kinds, TX, RX, O, R):
         pts = []
     elif kinds == (KIND_S,):
         pts = [slots[0]["c"]]
+    elif kinds == (KIND_D, KIND_D):
+        pts = list(_double_edge(TXg, RXg, slots[0]["a"], slots[0]["e"], slots[1]["a"], slots[1]["e"]))
     elif KIND_D in kinds:
         d = kinds.index(KIND_D)
         A = TXg

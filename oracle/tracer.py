@@ -17,6 +17,9 @@ interaction sequence; it is a path when:
   directions towards both neighbours lie in the wedge's exterior, their angle from the
   0-face (atan2 of the components along the 0-face normal and tangent) in [0, n pi];
   reflection points as above, back-tracked towards the edge point from both sides;
+* two diffractions (consecutive edges distinct): the points of the shortest path over both
+  edge lines (geometry.double_edge_points), each on its segment with its neighbours in its
+  wedge's exterior;
 * diffuse scattering from a tile whose front faces both terminals;
 * line of sight;
 
@@ -32,7 +35,7 @@ import math
 import numpy as np
 
 from .kinematics import terminal_state, body_poses, place_points, rotate
-from .geometry import dot, norm, reflection_chain, edge_point
+from .geometry import dot, norm, reflection_chain, edge_point, double_edge_points
 from .drt import extrapolate
 
 KIND_R, KIND_D, KIND_S = 1, 2, 3
@@ -138,6 +141,17 @@ def path_exists(ms, kinds, prims, visibility=True):
         c, cn = ms["c"][prims[:, 0]], ms["cn"][prims[:, 0]]
         ok &= (dot(TX - c, cn) > 0.0) & (dot(RX - c, cn) > 0.0)
         pts = [c]
+    elif kinds == (KIND_D, KIND_D):
+        e1, e2 = prims[:, 0], prims[:, 1]
+        Q1, Q2, z1, z2, conv = double_edge_points(TX, RX, ms["a"][e1], ms["e"][e1], ms["a"][e2], ms["e"][e2])
+        ok &= conv
+        for ed, z in ((e1, z1), (e2, z2)):
+            ok &= (z >= ms["zlim"][ed, 0]) & (z <= ms["zlim"][ed, 1])
+        if visibility:
+            for ed, Q, prev, nxt in ((e1, Q1, TX, Q2), (e2, Q2, Q1, RX)):
+                lim = ms["wn"][ed] * math.pi
+                ok &= (_wedge_angle(ms, ed, Q, prev) <= lim) & (_wedge_angle(ms, ed, Q, nxt) <= lim)
+        pts = [Q1, Q2]
     elif KIND_D in kinds:
         d = kinds.index(KIND_D)
         before = [(ms["p"][prims[:, i]], ms["n"][prims[:, i]]) for i in range(d)]
@@ -192,15 +206,18 @@ def pols_of(ms, kinds, prims):
     return tuple(out)
 
 
-def signatures(max_refl, max_refl_diff, scattering, los):
+def signatures(max_refl, max_refl_diff, scattering, los, double_diff=False):
     """Signature tuples in the tracer's order: LoS; reflections by count; one diffraction
-    with 0..max_refl_diff reflections, the edge at every position; scattering."""
+    with 0..max_refl_diff reflections, the edge at every position; two diffractions;
+    scattering."""
     sigs = [()] if los else []
     for n in range(1, max_refl + 1):
         sigs.append((KIND_R,) * n)
     for n in range(0, max_refl_diff + 1):
         for d in range(n + 1):
             sigs.append((KIND_R,) * d + (KIND_D,) + (KIND_R,) * (n - d))
+    if double_diff:
+        sigs.append((KIND_D, KIND_D))
     if scattering:
         sigs.append((KIND_S,))
     return sigs
@@ -213,19 +230,18 @@ def candidates(ms, kinds):
     ranges = [range(npl) if k == KIND_R else range(ned) if k == KIND_D else range(nti) for k in kinds]
     out = []
     for seq in itertools.product(*ranges):
-        if any(kinds[i] == KIND_R and kinds[i + 1] == KIND_R and seq[i] == seq[i + 1]
-               for i in range(len(seq) - 1)):
+        if any(kinds[i] == kinds[i + 1] != KIND_S and seq[i] == seq[i + 1] for i in range(len(seq) - 1)):
             continue
         out.append(seq)
     return np.array(out, dtype=np.int64).reshape(len(out), len(kinds))
 
 
-def trace(scene, t=0.0, max_refl=2, max_refl_diff=1, scattering=True, los=True):
+def trace(scene, t=0.0, max_refl=2, max_refl_diff=1, scattering=True, los=True, double_diff=False):
     """All paths at the instant t0 + t: list of (kinds, prims, pols, L) in the tracer's
     order (signature order of signatures(), then primitive indices lexicographically)."""
     ms = moved_scene(scene, t)
     out = []
-    for kinds in signatures(max_refl, max_refl_diff, scattering, los):
+    for kinds in signatures(max_refl, max_refl_diff, scattering, los, double_diff):
         cand = candidates(ms, kinds)
         if cand.shape[0] == 0:
             continue

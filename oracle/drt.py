@@ -45,6 +45,11 @@ from . import polar
 C0 = 299_792_458.0
 KIND_R, KIND_D, KIND_S = 1, 2, 3
 RHO_MIN = 1e-9  # a diffraction source/receiver closer than this to the edge line is degenerate
+# A wedge angle (Sec. III-B, the UTD angles from the 0-face) measured inside the wedge body
+# within this many radians of the 0-face is a direction along that face whose sign rounding
+# decided: it is read as on the face (a tiny negative angle, where the coefficient is
+# continuous) instead of near 2 pi.  Two edges of one face (a path along a roof) need this.
+FACE_EPS = 1e-5
 
 
 def freq_axis(f_c, bandwidth, n_sub):
@@ -55,6 +60,13 @@ def freq_axis(f_c, bandwidth, n_sub):
 
 def _unit(v):
     return v / norm(v)[..., None]
+
+
+def _wedge_angle(u, ed, wn):
+    """Angle of the edge-normal component u from the 0-face (tangent t towards normal n) in
+    [0, 2 pi), except inside the wedge body within FACE_EPS of 2 pi, read as on the 0-face."""
+    phi = np.mod(np.arctan2(dot(u, ed["n"]), dot(u, ed["t"])), 2.0 * math.pi)
+    return np.where((phi > wn * math.pi) & (phi > 2.0 * math.pi - FACE_EPS), phi - 2.0 * math.pi, phi)
 
 
 def _moved(scene, kind, prim, poses, k_axis):
@@ -259,9 +271,9 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
             sin_b0 = np.sqrt(np.maximum(1.0 - cos_b0 * cos_b0, 0.0))
             up = (prev - Q) - dot(prev - Q, e)[..., None] * e
             uo = (nxt - Q) - dot(nxt - Q, e)[..., None] * e
-            phi_p = np.mod(np.arctan2(dot(up, ed["n"]), dot(up, ed["t"])), 2.0 * math.pi)
-            phi = np.mod(np.arctan2(dot(uo, ed["n"]), dot(uo, ed["t"])), 2.0 * math.pi)
             wn = scene["edge_wedge_n"][prims[:, j]][:, None]
+            phi_p = _wedge_angle(up, ed, wn)
+            phi = _wedge_angle(uo, ed, wn)
             Ld = Ls[j] * sin_b0 ** 2
             if ants is None:
                 Ds.append(utd_coefficient(phi, phi_p, sin_b0, wn, k, Ld, pols[:, j][:, None]))
@@ -281,10 +293,10 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
         sin_b0 = np.sqrt(np.maximum(1.0 - cos_b0 * cos_b0, 0.0))
         up = (A - QD) - dot(A - QD, e)[..., None] * e
         uo = (B - QD) - dot(B - QD, e)[..., None] * e
-        phi_p = np.mod(np.arctan2(dot(up, ed["n"]), dot(up, ed["t"])), 2.0 * math.pi)
-        phi = np.mod(np.arctan2(dot(uo, ed["n"]), dot(uo, ed["t"])), 2.0 * math.pi)
-        Ld = s * sp * sin_b0 ** 2 / (s + sp)
         wn = scene["edge_wedge_n"][prims[:, d]][:, None]
+        phi_p = _wedge_angle(up, ed, wn)
+        phi = _wedge_angle(uo, ed, wn)
+        Ld = s * sp * sin_b0 ** 2 / (s + sp)
         if ants is None:
             D = utd_coefficient(phi, phi_p, sin_b0, wn, k, Ld, pols[:, d][:, None])
         else:

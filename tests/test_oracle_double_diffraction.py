@@ -149,3 +149,45 @@ def test_tracer_finds_and_blocks_the_path():
     s, _ = _two_screens(wall=True)
     p = oracle.trace(s, 0.0, max_refl=0, max_refl_diff=-1, scattering=False, los=False, double_diff=True)
     assert p == []
+
+
+def _roof(R, pol):
+    # two edges of one face (the roof z = 10 of a block between x = 0 and x = 2, edges along
+    # y, right-angle wedges n = 1.5 with the roof as 0-face); the whole scene turned by R
+    b = SceneBuilder()
+    e1 = b.add_edge(0, R @ (0.0, 0, 10), R @ (0.0, 1, 0), R @ (1.0, 0, 0), R @ (0.0, 0, 1), 1.5, zlim=(-5, 5))
+    e2 = b.add_edge(0, R @ (2.0, 0, 10), R @ (0.0, 1, 0), R @ (-1.0, 0, 0), R @ (0.0, 0, 1), 1.5, zlim=(-5, 5))
+    b.add_ray((KIND_D, KIND_D), (e1, e2), (pol, pol))
+    return b.build(tx_p=R @ (-5.0, 0, 5), rx_p=R @ (8.0, 0, 6))
+
+
+def _rotation(axis, ang):
+    a = np.asarray(axis, float) / np.linalg.norm(axis)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * K @ K
+
+
+def test_path_along_a_face_reads_grazing_angles():
+    # The segment between the edges runs along their common face: the exit angle at the
+    # first edge and the incidence angle at the second are 0 (grazing), whatever sign the
+    # rounding of a turned frame gives them.  Pinned to the UTD product at those angles
+    # (frame invariance: every turned copy gives the same coefficient).
+    k = 2 * math.pi / LAM
+    s0, s1, s2 = math.hypot(5, 5), 2.0, math.hypot(6, 4)
+    angles = [(0.0, 1.25 * math.pi), (math.atan2(-4.0, -6.0) % (2 * math.pi), 0.0)]   # (phi, phi') per edge
+    Ls = [s0 * s1 / (s0 + s1), (s0 + s1) * s2 / (s0 + s1 + s2)]
+    rng = np.random.default_rng(11)
+    want = []
+    for pol in (0, 1):
+        w = LAM / (4 * math.pi) / math.sqrt(s0 * s1 * s2 * (s0 + s1 + s2))
+        for (phi, phi_p), Lj in zip(angles, Ls):
+            w = w * utd_coefficient(np.array(phi), np.array(phi_p), np.array(1.0), 1.5, k, np.array(Lj), pol)
+        want.append(complex(w))
+    assert want[0] == 0 and abs(want[1]) > 0          # soft vanishes along the face
+    for pol in (0, 1):
+        for r in range(24):
+            R = np.eye(3) if r == 0 else _rotation(rng.normal(size=3), rng.uniform(0, 2 * math.pi))
+            ex = oracle.extrapolate(_roof(R, pol), np.array([0.0]), F_C)
+            assert ex["valid"][0, 0]
+            assert abs(ex["L"][0, 0] - (s0 + s1 + s2)) < 1e-12
+            assert abs(ex["gain"][0, 0] - want[pol]) <= 1e-9 * abs(want[1]), (pol, r)

@@ -170,7 +170,9 @@ int drt_destroy(drt_ctx *ctx);
 
 /* Validate, pack and upload a scene (Sec. II's dynamic environment database plus the t0
  * rays).  Errors: DRT_E_INVAL (index out of range, n_int > 4, more than one diffraction
- * in a ray, a scattering interaction that is not the ray's only one, non-unit vectors);
+ * in a ray other than a two-edge ray (exactly two distinct edges, solved as the shortest path
+ * over both edge lines), a scattering interaction that is not the ray's only one, non-unit
+ * vectors);
  * DRT_E_DEGENERATE (at t0 a reflection's image line is parallel to its wall, i.e. the
  * denominator y_TX + y_RX of eq. ref_point vanishes, or a diffraction source/receiver
  * lies on the edge line, d_TX + d_RX = 0 in eq. diff_point); DRT_E_INCONSISTENT (ray_q0
@@ -196,6 +198,7 @@ typedef struct {
                                  (the edge at every position); -1: none */
   int32_t scattering;         /* 1: single diffuse scattering from every tile */
   int32_t los;                /* 1: the line of sight */
+  int32_t double_diff;        /* 1: paths over two distinct edges (no reflection) */
 } drt_trace_opts;
 
 typedef struct {
@@ -213,13 +216,14 @@ typedef struct {
  * parameter lies in (0, 1), every reflection point lies in its wall's facet (walls without a
  * facet are unbounded) with both neighbouring vertices more than 1e-9 m in front of the wall,
  * the diffraction point lies on its edge segment with the directions to both neighbours in
- * the wedge's exterior (angle from the 0-face in [0, n pi]), a tile faces both terminals,
+ * the wedge's exterior (angle from the 0-face in [0, n pi]; for two edges, the points of
+ * the shortest path over both edge lines, each so), a tile faces both terminals,
  * and no wall's facet (or unbounded wall) crosses any segment of the path more than 1e-7 m
  * from both of its ends.  Creates a new resident scene (*new_scene): the primitives, bodies
  * and terminals of `scene` carried to t0 + t (body reference points, velocities and angular
  * speeds advanced; primitive indices unchanged) and one ray per path, ordered by class (line
  * of sight; 1..max_refl reflections; one diffraction with 0, 1, 2 reflections, edge first to
- * edge last; scattering) and then by primitive indices.  Polarisation flags: perpendicular
+ * edge last; two edges; scattering) and then by primitive indices.  Polarisation flags: perpendicular
  * for walls with |n_z| <= 0.5 and vertical edges (|e_z| > 0.5), parallel otherwise;
  * perpendicular for tiles.  Synchronous.  Errors: DRT_E_INVAL for options out of range or a
  * non-finite t; DRT_E_NOTFOUND; DRT_E_NOMEM. */

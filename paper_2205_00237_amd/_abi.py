@@ -79,7 +79,7 @@ class RayOut(C.Structure):
 
 class TraceOpts(C.Structure):
     _fields_ = [("max_refl", C.c_int32), ("max_refl_diff", C.c_int32), ("scattering", C.c_int32),
-                ("los", C.c_int32)]
+                ("los", C.c_int32), ("double_diff", C.c_int32)]
 
 
 class TraceInfo(C.Structure):
@@ -278,9 +278,9 @@ def drt_extrapolate(ctx, sid, n_rays, dt, n_steps, f_c, precision, out_ptrs, str
                                C.byref(o), C.c_void_p(int(stream))), "drt_extrapolate")
 
 
-def drt_trace(ctx, sid, t, max_refl, max_refl_diff, scattering, los):
+def drt_trace(ctx, sid, t, max_refl, max_refl_diff, scattering, los, double_diff=False):
     """Returns (new scene id, info dict)."""
-    o = TraceOpts(int(max_refl), int(max_refl_diff), int(bool(scattering)), int(bool(los)))
+    o = TraceOpts(int(max_refl), int(max_refl_diff), int(bool(scattering)), int(bool(los)), int(bool(double_diff)))
     new, info = C.c_uint32(), TraceInfo()
     _check(LIB.drt_trace(ctx, int(sid), float(t), C.byref(o), C.byref(new), C.byref(info)), "drt_trace")
     return new.value, {k: getattr(info, k) for k, _ in TraceInfo._fields_}
@@ -291,7 +291,8 @@ def drt_segments(ctx, sid, dt, n_steps, f_c, trace_opts, threshold_db, max_steps
     """[(first instant, length, scene id)] of the multipath lifetimes."""
     import numpy as np
     o = TraceOpts(int(trace_opts.get("max_refl", 2)), int(trace_opts.get("max_refl_diff", 1)),
-                  int(bool(trace_opts.get("scattering", True))), int(bool(trace_opts.get("los", True))))
+                  int(bool(trace_opts.get("scattering", True))), int(bool(trace_opts.get("los", True))),
+                  int(bool(trace_opts.get("double_diff", False))))
     r = RefreshOpts(float(threshold_db), int(max_steps), int(min_steps))
     start = np.zeros(max_segments, np.int32)
     length = np.zeros(max_segments, np.int32)

@@ -109,6 +109,8 @@ template <class F> DRT_HD J2<F> msqrt(J2<F> a) {
   return {r, r1, (a.dd - F(2) * r1 * r1) / (F(2) * r)};
 }
 template <class F> DRT_HD bool mfinite(J2<F> a) { return mfinite(a.v) && mfinite(a.d) && mfinite(a.dd); }
+template <class F> struct ScalarOf { using type = F; };
+template <class F> struct ScalarOf<J2<F>> { using type = F; };
 
 template <class F> struct V3 { F x, y, z; };
 template <class F> DRT_HD V3<F> v3(F x, F y, F z) { return V3<F>{x, y, z}; }
@@ -236,16 +238,86 @@ template <class F> struct ChainOut {
   V3<F> A, B;         // unfolded image source / receiver of the diffraction
   F rhoA, rhoB;
   F zQ;               // diffraction point along the edge from its reference point
+  F zQ2;              // the second edge's point (two-edge chains)
   bool ok, degen;
 };
 
-// Interaction points of an N-interaction chain with its diffraction at slot DP (DP < 0:
-// reflections only).  Sec. III-A.2 (images and back-tracking), Sec. III-B (eq. diff_point).
+constexpr int kDDIters = 16;        // Newton steps of the two-edge solve
+
+// Points of the shortest path TX -> edge 1 -> edge 2 -> RX (the two-edge extension of
+// Sec. III-B; Keller's law at both edges): Newton's method on (z1, z2) from each edge's
+// single-edge point, halving a step while it lengthens the path beyond rounding (the length
+// is convex in (z1, z2)).  Converged when both stationarity residuals are below tol.
+template <class F>
+DRT_HD void solve_two_edges(V3<F> TX, V3<F> RX, const Slot<F>& e1, const Slot<F>& e2, ChainOut<F>& c) {
+  auto single = [&](const Slot<F>& ed) {
+    const F zA = dot(TX - ed.p, ed.e), zB = dot(RX - ed.p, ed.e);
+    const F rA = norm((TX - ed.p) - zA * ed.e), rB = norm((RX - ed.p) - zB * ed.e);
+    const F z = zB + rB * (zA - zB) / (rA + rB);
+    return mfinite(z) ? z : F(0);
+  };
+  auto length = [&](F a, F b) {
+    const V3<F> Q1 = e1.p + a * e1.e, Q2 = e2.p + b * e2.e;
+    return norm(Q1 - TX) + norm(Q2 - Q1) + norm(RX - Q2);
+  };
+  F z1 = single(e1), z2 = single(e2), f = length(z1, z2), g1 = F(1), g2 = F(1);
+  const F up = F(1.0 + 1e-12);
+  for (int it = 0; it < kDDIters; ++it) {
+    const V3<F> Q1 = e1.p + z1 * e1.e, Q2 = e2.p + z2 * e2.e;
+    const V3<F> d0 = Q1 - TX, d1 = Q2 - Q1, d2 = RX - Q2;
+    const F l0 = norm(d0), l1 = norm(d1), l2 = norm(d2);
+    const F c0 = dot(d0, e1.e) / l0, c1a = dot(d1, e1.e) / l1, c1b = dot(d1, e2.e) / l1, c2 = dot(d2, e2.e) / l2;
+    g1 = c0 - c1a;
+    g2 = c1b - c2;
+    const F h11 = (F(1) - c0 * c0) / l0 + (F(1) - c1a * c1a) / l1;
+    const F h22 = (F(1) - c1b * c1b) / l1 + (F(1) - c2 * c2) / l2;
+    const F h12 = (c1a * c1b - dot(e1.e, e2.e)) / l1;
+    const F det = h11 * h22 - h12 * h12;
+    F s1 = (h12 * g2 - h22 * g1) / det, s2 = (h12 * g1 - h11 * g2) / det;
+    if (!mfinite(s1) || !mfinite(s2)) {
+      s1 = -g1;
+      s2 = -g2;
+    }
+    F lam = F(1), fn = length(z1 + s1, z2 + s2);
+    for (int h = 0; h < 40 && fn > f * up; ++h) {
+      lam = F(0.5) * lam;
+      fn = length(z1 + lam * s1, z2 + lam * s2);
+    }
+    z1 = z1 + lam * s1;
+    z2 = z2 + lam * s2;
+    f = fn;
+  }
+  const V3<F> Q1 = e1.p + z1 * e1.e, Q2 = e2.p + z2 * e2.e;
+  {   // residuals at the final points
+    const V3<F> d0 = Q1 - TX, d1 = Q2 - Q1, d2 = RX - Q2;
+    g1 = dot(d0, e1.e) / norm(d0) - dot(d1, e1.e) / norm(d1);
+    g2 = dot(d1, e2.e) / norm(d1) - dot(d2, e2.e) / norm(d2);
+  }
+  auto rho = [](V3<F> X, const Slot<F>& ed) {
+    const V3<F> w = X - ed.p;
+    return norm(w - dot(w, ed.e) * ed.e);
+  };
+  const bool far = rho(TX, e1) > F(kRhoMin) && rho(Q2, e1) > F(kRhoMin) && rho(Q1, e2) > F(kRhoMin) &&
+                   rho(RX, e2) > F(kRhoMin);
+  const F tol = F(sizeof(typename ScalarOf<F>::type) >= 8 ? 1e-12 : 1e-4);
+  const bool conv = g1 < tol && g1 > -tol && g2 < tol && g2 > -tol;
+  c.Q[0] = Q1;
+  c.Q[1] = Q2;
+  c.zQ = z1;
+  c.zQ2 = z2;
+  c.ok = far && conv;
+  c.degen = !far;
+}
+
+// Interaction points of an N-interaction chain with its diffraction at slot DP (DP = -1:
+// reflections only; DP = -2: two diffractions, slots 0 and 1).  Sec. III-A.2 (images and back-tracking), Sec. III-B (eq. diff_point).
 template <class F, int N, int DP>
 DRT_HD void solve_points(V3<F> TX, V3<F> RX, const Slot<F>* sl, ChainOut<F>& c) {
   c.ok = true;
   c.degen = false;
-  if constexpr (DP < 0) {
+  if constexpr (DP == -2) {
+    solve_two_edges<F>(TX, RX, sl[0], sl[1], c);
+  } else if constexpr (DP < 0) {
     reflect_chain<F, N>(TX, RX, sl, c.Q, c.ok, c.degen);
   } else {
     V3<F> A = TX;
@@ -376,6 +448,21 @@ template <class F, class G> DRT_HD Cx<G> cot_F(F beta, F sgn, F n, F inv_2pin, G
   sincos_small(eps * frcp(G(2) * nn), st, ctn);      // |eps / 2n| <= pi / 2
   Cx<G> fx = utd_transition(kL * (G(2) * h * h));
   return (ctn * frcp(st)) * fx;
+}
+
+// Wedge angle of the edge-normal component u from the 0-face (tangent t towards normal n) in
+// [0, 2 pi), except that an angle inside the wedge body within kFaceEps of 2 pi is a
+// direction along the 0-face whose sign rounding decided (two edges of one face, a path
+// along a roof): it is taken as the tiny negative angle, where the coefficient is
+// continuous with the face.
+constexpr double kFaceEps = 1e-5;
+template <class F>
+DRT_HD F utd_angle(const V3<F>& u, const Slot<F>& es, F wn) {
+  const F two_pi = F(2) * Consts<F>::pi;
+  F phi = matan2(dot(u, es.n), dot(u, es.t));
+  if (phi < F(0)) phi += two_pi;
+  if (phi > wn * Consts<F>::pi && phi > two_pi - F(kFaceEps)) phi -= two_pi;
+  return phi;
 }
 
 // Kouyoumjian-Pathak coefficient of a perfectly conducting wedge (soft for pol 0, hard for 1);
@@ -553,7 +640,7 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    if (SCAT || i == DP) continue;
+    if (SCAT || i == DP || DP == -2) continue;
     const DPlane& pl = sc.planes[ray.prim[i]];
     G ct = G(mfabs(dot(dv[i], sl[i].n))) * frcp(G(len[i]));
     if constexpr (POL) {
@@ -568,7 +655,7 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
     const V3<G> pr{G(sc.rx_ant[0]), G(sc.rx_ant[1]), G(sc.rx_ant[2])};
     return cdot(Ef, dipole_pattern(pr, gv(-kh[N])));
   };
-  if constexpr (POL && DP < 0) gam = receive(E);
+  if constexpr (POL && DP == -1) gam = receive(E);
   bool ok = ch.ok;
   Cx<G> a;
   if constexpr (SCAT) {
@@ -596,6 +683,39 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
     sincos_small(ph, sp_, cp_);     // tile phase in [0, 2 pi)
     a = cx<G>(sc_ * cp_, sc_ * sp_);
     if constexpr (POL) a = a * gam;   // the tile keeps the field: the two patterns' projection
+  } else if constexpr (DP == -2) {
+    // two edges: UTD for successive edges (non-slope), the second edge seeing the first
+    // edge's field as from the unfolded distance s0 + s1 (exact for parallel edges);
+    // spreading 1 / sqrt(s0 s1 s2 (s0 + s1 + s2))
+    const G k = G(2) * pi / lam;
+    const F Lsum = len[0] + len[1] + len[2];
+    const F Lpar[2] = {len[0] * len[1] / (len[0] + len[1]), (len[0] + len[1]) * len[2] / Lsum};
+    Cx<G> Dprod = cx<G>(G(1), G(0));
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const DEdge& ed = sc.edges[ray.prim[j]];
+      const Slot<F>& es = sl[j];
+      const V3<F> Q = ch.Q[j], dA = verts[j] - Q, dB = verts[j + 2] - Q;
+      const F cb = -dot(dA, es.e) / len[j];
+      const F sb2 = F(1) - cb * cb;
+      const F sb = msqrt(sb2 > F(0) ? sb2 : F(0));
+      const V3<F> up = dA - dot(dA, es.e) * es.e, uo = dB - dot(dB, es.e) * es.e;
+      const F phi_p = utd_angle(up, es, F(ed.wn)), phi = utd_angle(uo, es, F(ed.wn));
+      const G Ld = G(Lpar[j] * sb * sb);
+      if constexpr (POL) {
+        E = diffract_field(E, gv(kh[j]), gv(kh[j + 1]), gv(es.e),
+                           utd_coefficient<F, G>(phi, phi_p, G(sb), F(ed.wn), k, Ld, DRT_PERP),
+                           utd_coefficient<F, G>(phi, phi_p, G(sb), F(ed.wn), k, Ld, DRT_PAR));
+      } else {
+        Dprod = Dprod * utd_coefficient<F, G>(phi, phi_p, G(sb), F(ed.wn), k, Ld, ray.pol[j]);
+      }
+    }
+    const G scale = lam / (G(4) * pi) * frcp(msqrt(G(len[0] * len[1] * len[2] * Lsum)));
+    if constexpr (POL) {
+      a = scale * receive(E);
+    } else {
+      a = scale * Dprod;
+    }
   } else if constexpr (DP >= 0) {
     const DEdge& ed = sc.edges[ray.prim[DP]];
     const Slot<F>& es = sl[DP];
@@ -607,11 +727,7 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
     F sb = msqrt(sb2 > F(0) ? sb2 : F(0));
     V3<F> up = dA - dot(dA, es.e) * es.e;
     V3<F> uo = dB - dot(dB, es.e) * es.e;
-    const F piF = Consts<F>::pi;
-    F phi_p = matan2(dot(up, es.n), dot(up, es.t));
-    F phi = matan2(dot(uo, es.n), dot(uo, es.t));
-    if (phi_p < F(0)) phi_p += F(2) * piF;
-    if (phi < F(0)) phi += F(2) * piF;
+    const F phi_p = utd_angle(up, es, F(ed.wn)), phi = utd_angle(uo, es, F(ed.wn));
     G Ld = G(s * sp * sb * sb) * frcp(G(s + sp));
     G k = G(2) * pi / lam;
     G scale = lam / (G(4) * pi) * frcp(msqrt(G(sp * s * (sp + s))));
@@ -647,9 +763,10 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
     bool in = true;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      if (i == DP) {
+      if (i == DP || DP == -2) {
         const DEdge& ed = sc.edges[ray.prim[i]];
-        in = in && ch.zQ >= F(ed.zlo) && ch.zQ <= F(ed.zhi);
+        const F zq = (DP == -2 && i == 1) ? ch.zQ2 : ch.zQ;
+        in = in && zq >= F(ed.zlo) && zq <= F(ed.zhi);
         continue;
       }
       const V3<F> q = ch.Q[i], nn = sl[i].n;
@@ -760,6 +877,7 @@ template <class F, int CLS, class Fn> DRT_HD auto with_signature_in(int code, Fn
       case SIG_DRRR: return fn.template operator()<4, 0, false>();
       case SIG_RDRR: return fn.template operator()<4, 1, false>();
       case SIG_RRDR: return fn.template operator()<4, 2, false>();
+      case SIG_DD: return fn.template operator()<2, -2, false>();
       default: return fn.template operator()<4, 3, false>();
     }
   } else {
@@ -785,6 +903,7 @@ template <class F, class Fn> DRT_HD auto with_signature(int code, Fn&& fn) {
     case SIG_RDRR: return fn.template operator()<4, 1, false>();
     case SIG_RRDR: return fn.template operator()<4, 2, false>();
     case SIG_RRRD: return fn.template operator()<4, 3, false>();
+    case SIG_DD: return fn.template operator()<2, -2, false>();
     default: return fn.template operator()<1, -1, true>();
   }
 }

@@ -118,7 +118,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 // Snapshot tracer.  One signature of candidate interaction sequences: the index of a
 // candidate is a mixed-radix number whose digit i (most significant first) picks the
 // primitive of interaction i: a wall (radix = walls, or walls - 1 after another wall, the
-// previous wall being skipped), an edge or a tile.  Ascending indices are lexicographic
+// previous wall being skipped), an edge (likewise after another edge) or a tile.  Ascending indices are lexicographic
 // in the primitive indices.
 struct TraceSig {
   int32_t n, code;
@@ -138,7 +138,7 @@ __host__ __device__ inline void trace_decode(const TraceSig& g, int64_t c, int32
   }
   for (int i = 0; i < g.n; ++i) {
     int32_t p = dig[i];
-    if (g.kind[i] == DRT_R && i > 0 && g.kind[i - 1] == DRT_R) p += (p >= prim[i - 1]) ? 1 : 0;
+    if (i > 0 && g.kind[i] == g.kind[i - 1]) p += (p >= prim[i - 1]) ? 1 : 0;
     prim[i] = p;
   }
 }

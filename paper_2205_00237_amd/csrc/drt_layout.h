@@ -44,7 +44,7 @@ struct DTile {          // 88 B
 enum SigCode : uint8_t {
   SIG_LOS = 0, SIG_R1, SIG_R2, SIG_R3, SIG_R4,
   SIG_D, SIG_DR, SIG_RD, SIG_DRR, SIG_RDR, SIG_RRD, SIG_DRRR, SIG_RDRR, SIG_RRDR, SIG_RRRD,
-  SIG_S, SIG_COUNT
+  SIG_S, SIG_DD, SIG_COUNT
 };
 
 // Signature classes launched as separate kernels so that each gets its own register budget.

@@ -208,6 +208,7 @@ static int sig_code(int nint, const uint8_t* kind, int* dpos) {
   *dpos = 255;
   if (nint == 0) return SIG_LOS;
   if (kind[0] == DRT_S) return SIG_S;
+  if (nint == 2 && kind[0] == DRT_D && kind[1] == DRT_D) return SIG_DD;
   int d = -1;
   for (int i = 0; i < nint; ++i)
     if (kind[i] == DRT_D) d = i;
@@ -360,7 +361,9 @@ static int validate_and_pack(const drt_scene_desc* d, Scene& s) {
       R.prim[i] = p;
       R.body[i] = k == DRT_R ? planes[p].body : k == DRT_D ? edges[p].body : tiles[p].body;
     }
-    if (nd > 1) return fail(DRT_E_INVAL, "ray %d: more than one diffraction", r);
+    if (nd > 1 && !(nd == 2 && n == 2))
+      return fail(DRT_E_INVAL, "ray %d: two diffractions only as a two-edge ray, one diffraction otherwise", r);
+    if (nd == 2 && R.prim[0] == R.prim[1]) return fail(DRT_E_INVAL, "ray %d: the two edges must differ", r);
     if (ns > 0 && n != 1) return fail(DRT_E_INVAL, "ray %d: scattering must be the only interaction", r);
     R.nint = uint8_t(n);
     int dpos;
@@ -1162,6 +1165,7 @@ static std::vector<TraceSig> trace_signatures(const drt_trace_opts& o, int np, i
       k[d] = DRT_D;
       kinds.push_back(k);
     }
+  if (o.double_diff) kinds.push_back({DRT_D, DRT_D});
   if (o.scattering) kinds.push_back({DRT_S});
   std::vector<TraceSig> sigs;
   for (const auto& k : kinds) {
@@ -1172,8 +1176,8 @@ static std::vector<TraceSig> trace_signatures(const drt_trace_opts& o, int np, i
     for (int i = 0; i < g.n; ++i) {
       g.kind[i] = k[i];
       k8[i] = uint8_t(k[i]);
-      const bool after_wall = i > 0 && k[i - 1] == DRT_R;
-      g.radix[i] = k[i] == DRT_R ? (after_wall ? np - 1 : np) : (k[i] == DRT_D ? ne : nt);
+      const bool repeat = i > 0 && k[i - 1] == k[i];     // consecutive walls (edges) differ
+      g.radix[i] = (k[i] == DRT_R ? np : (k[i] == DRT_D ? ne : nt)) - (repeat ? 1 : 0);
       g.count = g.radix[i] > 0 ? g.count * g.radix[i] : 0;
     }
     int dpos;

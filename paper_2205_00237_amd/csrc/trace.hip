@@ -60,7 +60,8 @@ __device__ __forceinline__ bool path_geometry(const SceneView& sc, const int32_t
   } else {
     Slot<double> sl[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) load_slot_t0(sc, SCAT ? DRT_S : (i == DP ? DRT_D : DRT_R), prim[i], sl[i]);
+    for (int i = 0; i < N; ++i)
+      load_slot_t0(sc, SCAT ? DRT_S : ((i == DP || DP == -2) ? DRT_D : DRT_R), prim[i], sl[i]);
     if constexpr (SCAT) {
       V[1] = sl[0].p;
       return dot(TX - sl[0].p, sl[0].n) > 0.0 && dot(RX - sl[0].p, sl[0].n) > 0.0;
@@ -72,7 +73,12 @@ __device__ __forceinline__ bool path_geometry(const SceneView& sc, const int32_t
       for (int i = 0; i < N; ++i) V[i + 1] = ch.Q[i];
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        if (i == DP) {
+        if (DP == -2) {   // two edges: each point on its segment, neighbours in its exterior
+          const DEdge& E = sc.edges[prim[i]];
+          const double lim = E.wn * M_PI, zq = i == 0 ? ch.zQ : ch.zQ2;
+          ok = ok && zq >= E.zlo && zq <= E.zhi;
+          ok = ok && wedge_angle(sl[i], ch.Q[i], V[i]) <= lim && wedge_angle(sl[i], ch.Q[i], V[i + 2]) <= lim;
+        } else if (i == DP) {
           const DEdge& E = sc.edges[prim[i]];
           const double lim = E.wn * M_PI;
           ok = ok && ch.zQ >= E.zlo && ch.zQ <= E.zhi;
@@ -181,6 +187,7 @@ hipError_t launch_trace_cand(const SceneView& sc, const TraceSig& g, int sig_id,
     CAND(SIG_RDR, 3, 1, false)
     CAND(SIG_RRD, 3, 2, false)
     CAND(SIG_S, 1, -1, true)
+    CAND(SIG_DD, 2, -2, false)
 #undef CAND
     default:
       return hipErrorInvalidValue;

@@ -77,10 +77,10 @@ class Context:
                              {k: v.data_ptr() for k, v in out.items()}, _stream(stream))
         return out
 
-    def trace(self, sid, t=0.0, max_refl=2, max_refl_diff=1, scattering=True, los=True):
+    def trace(self, sid, t=0.0, max_refl=2, max_refl_diff=1, scattering=True, los=True, double_diff=False):
         """Snapshot trace at the scene's t0 + t: a new resident scene (the primitives carried
         to that instant, one ray per path found).  Returns (new scene id, info dict)."""
-        new, info = _abi.drt_trace(self.ctx, sid, t, max_refl, max_refl_diff, scattering, los)
+        new, info = _abi.drt_trace(self.ctx, sid, t, max_refl, max_refl_diff, scattering, los, double_diff)
         self.n_rays[new] = info["n_paths"]
         return new, info
 

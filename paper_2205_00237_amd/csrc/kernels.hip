@@ -52,6 +52,9 @@ struct RecM {
   float amp, phi0, p16B, p16_1;
   double phiB, phi1;
 };
+// The same 32 bytes as four 64-bit words (amp | phi0, p16B | p16_1, phiB, phi1).
+struct RecW { uint64_t w[4]; };
+static_assert(sizeof(RecM) == sizeof(RecW), "RecM is four 64-bit words");
 struct RecD { double L, gr, gi, zr, zi; };              // binary64: 40 B
 struct RecN { float L, gr, gi, zr, zi, pad; };          // naive binary32: 24 B
 
@@ -519,8 +522,38 @@ __device__ __forceinline__ float resid_hi(unsigned h, float x) {
   asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(x));
   return r;
 }
+// Compile-time loop: f(IC<I>{}) for I = B .. E-1.
+template <int V> struct IC { static constexpr int value = V; };
+template <int B, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+  if constexpr (B < E) {
+    f(IC<B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Value of lane 16 (l / 16) + S for lane l: DPP row_newbcast, a vector-ALU move within each
+// row of 16 lanes.  Every row and bank is enabled and every lane's source exists, so every
+// lane is written and the old value (bound_ctrl set: none is read) needs no initialisation.
+template <int S>
+__device__ __forceinline__ uint64_t row_bcast(uint64_t x) {
+  static_assert(S >= 0 && S < 16, "row position");
+  return __builtin_amdgcn_update_dpp(uint64_t(0), x, 0x150 + S, 0xF, 0xF, true);
+}
+
 __device__ __forceinline__ unsigned pk16(float x, float y) {
   return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(x, y));
+}
+
+// The lo word of (x, y) straight from the hi word: each half is the binary32 residual
+// -hi * 1 + x formed and rounded to binary16 by one mixed-precision FMA that writes only
+// that half of the destination (mixlo, then mixhi), so the pair costs two instructions.
+__device__ __forceinline__ unsigned lo_word(unsigned h, float x, float y) {
+  unsigned d;
+  asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixhi_f16 %0, -%1, 1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+      : "=&v"(d) : "v"(h), "v"(x), "v"(y));
+  return d;
 }
 
 // (x, y) -> hi, lo words of (x, y); with rot, also those of (-y, x): rounding toward zero
@@ -530,6 +563,10 @@ template <bool ROT>
 __device__ __forceinline__ Split16 split_pair(float x, float y) {
   Split16 w;
   w.hi = pk16(x, y);
+  if constexpr (!ROT) {
+    w.lo = lo_word(w.hi, x, y);
+    return w;
+  }
   const float rx = resid_lo(w.hi, x), ry = resid_hi(w.hi, y);
   w.lo = pk16(rx, ry);
   if constexpr (ROT) {
@@ -567,9 +604,14 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+  // lane 16 g + 4 b + j loads ray 16 b + 4 g + j of each batch of 64 (the same cache lines
+  // as a plain load): the four rays of block b that the lanes of row g consume then sit in
+  // row g, at positions 4 b .. 4 b + 3, and DPP row broadcasts hand them over without LDS
+  const int pl = 16 * ((lane >> 2) & 3) + 4 * grp + (lane & 3);
+  const RecW* rw = reinterpret_cast<const RecW*>(rt);
   auto load = [&](int rb) {
-    int r = rb + lane;
-    return r < r1 ? rt[r] : RecM{0.f, 0.f, 0.f, 0.f, 0.0, 0.0};
+    const int r = rb + pl;
+    return r < r1 ? rw[r] : RecW{0ull, 0ull, 0ull, 0ull};
   };
   float amax = 0.f;
   for (int rb = r0 + lane; rb < r1; rb += 64) amax = fmaxf(amax, rt[rb].amp);
@@ -579,33 +621,36 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
   (void)frexpf(amax, &e2);                       // amax < 2^e2
   const float kScale = amax > 0.f ? ldexpf(1.f, 13 - e2) : 1.f;
   const float kInv = 1.f / kScale;
-  RecM cur = load(r0);
+  RecW cur = load(r0);
   for (int rb = r0; rb < r1; rb += 64) {
-    RecM nxt = load(rb + 64);
+    RecW nxt = load(rb + 64);
     const int nblk = min(4, (r1 - rb + 15) >> 4);
-    for (int bk = 0; bk < nblk; ++bk) {
+    static_for<0, 4>([&](auto BK) {
+      constexpr int bk = decltype(BK)::value;
+      if (bk >= nblk) return;
       // U operands of the 16 rays (lane: rays 4 grp .. 4 grp + 3 of the block) for every
       // row tile; the V column phases' bases, kept for the column-tile loop below
       u32x4 ahw[MT], alw[MT];
       float vb[4], vs[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int src = bk * 16 + grp * 4 + j;
-        const float amp = __shfl(cur.amp, src) * kScale;
-        const float phi0 = __shfl(cur.phi0, src), p16B = __shfl(cur.p16B, src);
-        const double phiB = __shfl(cur.phiB, src), phi1 = __shfl(cur.phi1, src);
-        vs[j] = __shfl(cur.p16_1, src);
+      static_for<0, 4>([&](auto J) {
+        constexpr int j = decltype(J)::value, S = 4 * bk + j;
+        const uint64_t w0 = row_bcast<S>(cur.w[0]), w1 = row_bcast<S>(cur.w[1]);
+        const double phiB = __builtin_bit_cast(double, row_bcast<S>(cur.w[2]));
+        const double phi1 = __builtin_bit_cast(double, row_bcast<S>(cur.w[3]));
+        const float amp = __uint_as_float(uint32_t(w0)) * kScale, phi0 = __uint_as_float(uint32_t(w0 >> 32));
+        const float p16B = __uint_as_float(uint32_t(w1));
+        vs[j] = __uint_as_float(uint32_t(w1 >> 32));
         const float u0 = row_phase(m, phiB, phi0);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          float ph = __builtin_fmaf(float(mt), p16B, u0);
-          float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
-          Split16 w = split_pair<false>(amp * c, -(amp * s));   // U = |a| e^{-j 2 pi ph}
+          const float ph = mt == 0 ? u0 : __builtin_fmaf(float(mt), p16B, u0);
+          float sn = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
+          Split16 w = split_pair<false>(amp * c, -(amp * sn));   // U = |a| e^{-j 2 pi ph}
           ahw[mt][j] = w.hi;
           alw[mt][j] = w.lo;
         }
-        vb[j] = row_phase(NT == 1 ? (m & 7) : m, phi1, 0.f);
-      }
+        vb[j] = float(__builtin_amdgcn_fract(double(NT == 1 ? (m & 7) : m) * phi1));
+      });
       half8 ah[MT], al[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
@@ -619,15 +664,15 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
         u32x4 h0, l0, h1, l1;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          float ph = __builtin_fmaf(float(hh), vs[j], vb[j]);
-          float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
+          const float ph = hh == 0 ? vb[j] : __builtin_fmaf(float(hh), vs[j], vb[j]);
+          float sn = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
           if constexpr (NT == 1) {
             // C_re column: (V_re, -V_im) = (c, s); C_im column: (V_im, V_re) = (-s, c)
-            Split16 w = (m >> 3) == 0 ? split_pair<false>(c, s) : split_pair<false>(-s, c);
+            Split16 w = (m >> 3) == 0 ? split_pair<false>(c, sn) : split_pair<false>(-sn, c);
             h0[j] = w.hi;
             l0[j] = w.lo;
           } else {
-            Split16 w = split_pair<true>(c, s);
+            Split16 w = split_pair<true>(c, sn);
             h0[j] = w.hi;
             l0[j] = w.lo;
             h1[j] = w.rhi;
@@ -652,7 +697,7 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
           }
         }
       }
-    }
+    });
     cur = nxt;
   }
 #pragma unroll

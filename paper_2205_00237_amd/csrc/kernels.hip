@@ -545,17 +545,6 @@ __device__ __forceinline__ unsigned pk16(float x, float y) {
   return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(x, y));
 }
 
-// The lo word of (x, y) straight from the hi word: each half is the binary32 residual
-// -hi * 1 + x formed and rounded to binary16 by one mixed-precision FMA that writes only
-// that half of the destination (mixlo, then mixhi), so the pair costs two instructions.
-__device__ __forceinline__ unsigned lo_word(unsigned h, float x, float y) {
-  unsigned d;
-  asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]\n\t"
-      "v_fma_mixhi_f16 %0, -%1, 1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
-      : "=&v"(d) : "v"(h), "v"(x), "v"(y));
-  return d;
-}
-
 // (x, y) -> hi, lo words of (x, y); with rot, also those of (-y, x): rounding toward zero
 // commutes with negation, so the rotated pair splits into the rotated halves
 struct Split16 { unsigned hi, lo, rhi, rlo; };
@@ -563,10 +552,6 @@ template <bool ROT>
 __device__ __forceinline__ Split16 split_pair(float x, float y) {
   Split16 w;
   w.hi = pk16(x, y);
-  if constexpr (!ROT) {
-    w.lo = lo_word(w.hi, x, y);
-    return w;
-  }
   const float rx = resid_lo(w.hi, x), ry = resid_hi(w.hi, y);
   w.lo = pk16(rx, ry);
   if constexpr (ROT) {

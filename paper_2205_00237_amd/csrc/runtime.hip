@@ -861,6 +861,14 @@ int drt_create(int device, uint64_t hbm_cap_bytes, drt_ctx** out) {
     else if (!std::strcmp(k, "mfma16")) c->split_path = CFR_MFMA16;
     else return fail(DRT_E_INVAL, "DRT_CFR_KERNEL=%s: expected valu, mfma32 or mfma16", k);
   }
+  // tuning knob: waves the ray sum aims for (sets the number of ray groups per instant)
+  if (const char* w = std::getenv("DRT_TARGET_WAVES")) {
+    char* end = nullptr;
+    const long v = std::strtol(w, &end, 10);
+    if (end == w || *end != '\0' || v < 64 || v > (1L << 24))
+      return fail(DRT_E_INVAL, "DRT_TARGET_WAVES=%s: expected an integer in [64, 16777216]", w);
+    c->target_waves = int(v);
+  }
   *out = c.release();
   return DRT_OK;
 }

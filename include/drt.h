@@ -163,10 +163,11 @@ typedef struct {
 
 /* Create a context on HIP device `device`.  hbm_cap_bytes bounds the device memory the
  * context holds (resident scenes, scratch, in-flight requests); 0 = 90% of the device.
- * Two environment variables, read here, tune the split ray sum: DRT_CFR_KERNEL (mfma16, the
- * default; mfma32; valu) picks its kernel, DRT_TARGET_WAVES (64 .. 2^24) the number of
- * waves it aims for, which sets how many ray groups share an instant; a malformed value
- * fails the call with DRT_E_INVAL. */
+ * Three environment variables, read here, are tuning knobs: DRT_CFR_KERNEL (mfma16, the
+ * default; mfma32; valu) picks the split ray-sum kernel, DRT_TARGET_WAVES (64 .. 2^24) the
+ * number of waves it aims for, which sets how many ray groups share an instant, and
+ * DRT_BATCH_SAMPLES (1e6 .. 1e13, default 4e9) the rays x instants x subcarriers one serving
+ * batch may hold; a malformed value fails the call with DRT_E_INVAL. */
 int drt_create(int device, uint64_t hbm_cap_bytes, drt_ctx **out);
 
 /* Destroy a context: waits for in-flight work, frees every scene and scratch buffer. */

@@ -141,6 +141,7 @@ struct drt_ctx {
   std::map<hipStream_t, Scratch> scratch;   // per caller stream (drt_extrapolate / drt_cfr)
   std::mutex scratch_mu;
   int target_waves = 16384;
+  double batch_samples = 4e9;                // work cap of one serving batch (DRT_BATCH_SAMPLES)
   int split_path = CFR_MFMA16;               // ray-sum kernel of DRT_SPLIT (DRT_CFR_KERNEL)
 
   // kernel timing
@@ -570,7 +571,6 @@ static int check_prec(int prec, const Scene* s = nullptr) {
 static void serve_loop(drt_ctx* c);
 
 constexpr int kSlots = 4;
-constexpr double kBatchSamples = 4e9;   // work cap of one batch (the first request always fits)
 
 // Capture the batch kernels of one slot into a graph, one chain on the slot's stream: pose,
 // the geometry classes, the ray-sum tile shapes, the partial-sum reduction.  The node of
@@ -706,7 +706,7 @@ static bool launch_next(drt_ctx* c, Slot_& sl) {
       if (i == 0) p = hp;
       else if (!batchable(c, q, &p)) break;
       double w = double(q->r.n_rays) * q->r.tg.n_steps * q->r.fg.n_sub;
-      if (i > 0 && work + w > kBatchSamples) break;
+      if (i > 0 && work + w > c->batch_samples) break;   // the first request always fits
       if (arena + al(p.total) > budget) {
         if (i == 0) return false;
         break;
@@ -868,6 +868,14 @@ int drt_create(int device, uint64_t hbm_cap_bytes, drt_ctx** out) {
     if (end == w || *end != '\0' || v < 64 || v > (1L << 24))
       return fail(DRT_E_INVAL, "DRT_TARGET_WAVES=%s: expected an integer in [64, 16777216]", w);
     c->target_waves = int(v);
+  }
+  // tuning knob: samples (rays x instants x subcarriers) one serving batch may hold
+  if (const char* w = std::getenv("DRT_BATCH_SAMPLES")) {
+    char* end = nullptr;
+    const double v = std::strtod(w, &end);
+    if (end == w || *end != '\0' || !(v >= 1e6 && v <= 1e13))
+      return fail(DRT_E_INVAL, "DRT_BATCH_SAMPLES=%s: expected a number in [1e6, 1e13]", w);
+    c->batch_samples = v;
   }
   *out = c.release();
   return DRT_OK;

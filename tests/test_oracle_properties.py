@@ -66,7 +66,7 @@ bodies = st.fixed_dictionaries({
     "tx_v": st.tuples(*[st.floats(-15, 15, allow_nan=False)] * 3), "rx_v": st.tuples(*[st.floats(-15, 15, allow_nan=False)] * 3)})
 
 
-@settings(max_examples=80, deadline=None, suppress_health_check=[HealthCheck.filter_too_much])
+@settings(max_examples=80, deadline=None, derandomize=True, suppress_health_check=[HealthCheck.filter_too_much])
 @given(p0=vec, n0=unitish, tx_off=vec, rx_off=vec, hT=st.floats(0.5, 30), hR=st.floats(0.5, 30), body=bodies)
 def test_single_reflection_invariants(p0, n0, tx_off, rx_off, hT, hR, body):
     s, p0, n0 = _wall_scene(p0, n0, tx_off, rx_off, hT, hR, body)
@@ -80,9 +80,13 @@ def test_single_reflection_invariants(p0, n0, tx_off, rx_off, hT, hR, body):
         p, n = _wall_at(t[j], p0, n0, body)
         scale = 1.0 + np.abs(Q[j]).max()
         assert abs(np.dot(Q[j] - p, n)) < 1e-11 * scale        # on the moved wall
+        leg = min(np.linalg.norm(Q[j] - TX[j]), np.linalg.norm(RX[j] - Q[j]))
+        if leg < 1e-6:                 # a terminal on the wall: no direction to check
+            continue
         u_in = _unit(Q[j] - TX[j])
         u_out = _unit(RX[j] - Q[j])
-        assert np.abs(u_out - (u_in - 2 * np.dot(u_in, n) * n)).max() < 1e-10    # Snell
+        # Snell; the directions carry the points' rounding divided by the leg length
+        assert np.abs(u_out - (u_in - 2 * np.dot(u_in, n) * n)).max() < 1e-10 + 1e-13 * scale / leg
         L = np.linalg.norm(Q[j] - TX[j]) + np.linalg.norm(RX[j] - Q[j])
         img = TX[j] - 2 * np.dot(TX[j] - p, n) * n
         assert abs(out["L"][0, j] - L) < 1e-11 * scale                          # Fermat
@@ -107,7 +111,7 @@ def _length_independent(s, t, p0, n0, body):
     return np.linalg.norm(RX - (TX - 2 * np.dot(TX - p, n) * n))
 
 
-@settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.filter_too_much])
+@settings(max_examples=40, deadline=None, derandomize=True, suppress_health_check=[HealthCheck.filter_too_much])
 @given(p0=vec, n0=unitish, tx_off=vec, rx_off=vec, hT=st.floats(0.5, 30), hR=st.floats(0.5, 30),
        slide=st.floats(-20, 20), w0=st.floats(0.05, 1.0), wdot=st.floats(-0.5, 0.5))
 def test_turning_wall_doppler(p0, n0, tx_off, rx_off, hT, hR, slide, w0, wdot):

@@ -290,8 +290,12 @@ template <class A> struct AccT;
 template <> struct AccT<double> { using C = double2; };
 template <> struct AccT<float> { using C = float2; };
 
+// Three waves per SIMD: the LDS of the slice reduction (48 KiB in binary64) admits three
+// workgroups per CU, and capping the registers to match (168) lets all of them run, where
+// the unconstrained allocation (256 registers) held two.
 template <int PREC, int NK>
-__global__ __launch_bounds__(256) void k_cfr(const void* rec, CfrArgs a, void* out) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void k_cfr(const void* rec, CfrArgs a, void* out) {
   using F = typename std::conditional<PREC == DRT_FP64, double, float>::type;
   using C = typename AccT<F>::C;
   __shared__ C red[3][64][NK];

@@ -63,9 +63,10 @@ def measured_traffic(kernel):
         with open(TRAFFIC_FILE) as f:
             text = f.read()
         rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        src = kernel_source_hash()
     except (OSError, IndexError, ValueError):
         return None
-    if rec.get("kernel") != kernel or rec.get("source_sha256_16") != kernel_source_hash():
+    if rec.get("kernel") != kernel or rec.get("source_sha256_16") != src:
         return None
     return rec.get("hbm_bytes_per_launch")
 

@@ -13,6 +13,8 @@ enum GeomMode { GEOM_EXTRAP = 0, GEOM_ANCHOR = 1, GEOM_ANCHOR_MFMA = 2, GEOM_KIN
 enum CfrPath { CFR_VALU = 0, CFR_MFMA = 1, CFR_MFMA16 = 2 };
 
 constexpr int kNK = 16;          // subcarriers walked by one lane from its phase anchor
+constexpr int kNK64 = 32;        // the same in binary64 (its phase anchor costs a binary64 sincos)
+inline int nk_of(int prec) { return prec == DRT_FP64 ? kNK64 : kNK; }
 constexpr int kMinSlice = 8;     // fewest rays per wave slice of the ray sum
 
 struct ExtrapOut {
@@ -30,7 +32,7 @@ struct ExtrapOut {
   int spb, n_dop, n_delay, gate;
 };
 
-// Partition of H = sum over rays: a wave owns TTc instants x (KB * kNK) subcarriers of one
+// Partition of H = sum over rays: a wave owns TTc instants x (KB * nk_of(prec)) subcarriers of one
 // ray slice; a workgroup = 4 waves = 4 consecutive slices of one tile, summed in LDS; G
 // slice groups per tile are summed afterwards by k_reduce when G > 1.
 struct CfrArgs {

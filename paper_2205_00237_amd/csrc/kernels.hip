@@ -298,7 +298,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 void k_cfr(const void* rec, CfrArgs a, void* out) {
   using F = typename std::conditional<PREC == DRT_FP64, double, float>::type;
   using C = typename AccT<F>::C;
-  __shared__ C red[3][64][NK];
+  constexpr int NH = sizeof(C) * NK > 256 ? NK / 2 : NK;   // subcarriers per LDS pass (48 KiB at most)
+  __shared__ C red[3][64][NH];
   int bid = xcd_remap(blockIdx.x, gridDim.x);
   if (bid >= a.n_blocks) return;
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -358,7 +359,7 @@ void k_cfr(const void* rec, CfrArgs a, void* out) {
   // power, p_{i+1} = 2 cos(theta) p_i - p_{i-1} (z + 1/z = 2 cos theta for |z| = 1): one FMA per
   // component and step instead of a complex product; its rounding grows like i eps / sin theta,
   // below 1e-12 for the 16 steps at any delay of a metre or more
-  constexpr int W = 4;
+  constexpr int W = NK > 16 ? 2 : 4;
   int r = r0;
   for (; r + W <= r1; r += W) {
     F pr[W], pi[W], zr[W], zi[W];
@@ -423,23 +424,29 @@ void k_cfr(const void* rec, CfrArgs a, void* out) {
       pr = nr;
     }
   }
-  // sum the 4 waves' ray slices: waves 1..3 park their partial sums in LDS
-  if (wv > 0) {
+  // sum the 4 waves' ray slices: waves 1..3 park their partial sums in LDS, NH subcarriers
+  // per pass
 #pragma unroll
-    for (int i = 0; i < NK; ++i) red[wv - 1][lane][i] = C{acc_re[i], acc_im[i]};
-  }
-  __syncthreads();
-  if (wv != 0) return;
+  for (int h = 0; h < NK; h += NH) {
+    if (h > 0) __syncthreads();                  // wave 0 has read the previous pass
+    if (wv > 0) {
 #pragma unroll
-  for (int w = 0; w < 3; ++w) {
+      for (int i = 0; i < NH; ++i) red[wv - 1][lane][i] = C{acc_re[h + i], acc_im[h + i]};
+    }
+    __syncthreads();
+    if (wv == 0) {
 #pragma unroll
-    for (int i = 0; i < NK; ++i) {
-      C v = red[w][lane][i];
-      acc_re[i] += v.x;
-      acc_im[i] += v.y;
+      for (int w = 0; w < 3; ++w) {
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+          C v = red[w][lane][i];
+          acc_re[h + i] += v.x;
+          acc_im[h + i] += v.y;
+        }
+      }
     }
   }
-  if (t >= a.T) return;
+  if (wv != 0 || t >= a.T) return;
   C* dst = reinterpret_cast<C*>(out) + (a.G > 1 ? size_t(g) * a.T * a.K : 0) + size_t(t) * a.K;
 #pragma unroll
   for (int i = 0; i < NK; ++i) {
@@ -1081,7 +1088,8 @@ CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_wave
     a.n_blocks = int(tiles * G);
     return a;
   }
-  int blocks_k = (K + kNK - 1) / kNK;   // subcarrier blocks of kNK
+  const int nk = nk_of(prec);
+  int blocks_k = (K + nk - 1) / nk;     // subcarrier blocks of nk
   int kb = 1;
   while (kb < blocks_k && kb < 64) kb <<= 1;
   a.KB = kb;
@@ -1121,7 +1129,7 @@ hipError_t launch_cfr(const void* rec, const CfrArgs& a, int prec, void* out, hi
     return hipErrorInvalidValue;
   }
   if (prec == DRT_FP64)
-    hipLaunchKernelGGL((k_cfr<DRT_FP64, kNK>), dim3(grid), dim3(256), 0, st, rec, a, out);
+    hipLaunchKernelGGL((k_cfr<DRT_FP64, kNK64>), dim3(grid), dim3(256), 0, st, rec, a, out);
   else if (prec == DRT_SPLIT)
     hipLaunchKernelGGL((k_cfr<DRT_SPLIT, kNK>), dim3(grid), dim3(256), 0, st, rec, a, out);
   else

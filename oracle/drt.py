@@ -255,13 +255,18 @@ def _solve_group(scene, rays, kinds, TX, VTX, RX, VRX, poses, f_c):
             a = a * gam
         valid &= (cos_ti > 0.0) & (cos_ts > 0.0)
     elif "dd" in extra:
-        # UTD for successive edges, non-slope: the field diffracted by the first edge reaches
-        # the second as from a source at the unfolded distance s0 + s1 (exact for parallel
-        # edges), so D1 uses L1 = s0 s1 sin^2 b1 / (s0 + s1), D2 uses
-        # L2 = (s0 + s1) s2 sin^2 b2 / (s0 + s1 + s2), and the spreading is
-        # 1 / sqrt(s0 s1 s2 (s0 + s1 + s2))
+        # UTD for successive edges, non-slope.  The field diffracted by the first edge
+        # reaches the second as an astigmatic wave: one caustic on the first edge (principal
+        # radius s1), the other at the source's distance s0 + s1, which for parallel edges is
+        # also its radius of curvature in the second edge's plane of incidence.  The
+        # Kouyoumjian-Pathak distance parameter of such a wave,
+        # L = s (r_e + s) r_1 r_2 sin^2 b / (r_e (r_1 + s) (r_2 + s)), then gives
+        # L1 = s0 s1 sin^2 b1 / (s0 + s1) (a point source) and L2 = s1 s2 sin^2 b2 / (s1 + s2),
+        # and the spreading sqrt(r_e / (s (r_e + s))) of each edge gives
+        # 1 / sqrt(s0 s1 s2 (s0 + s1 + s2)) overall (exact for parallel edges, an
+        # approximation otherwise)
         s0, s1, s2 = lens
-        Ds, Ls = [], [s0 * s1 / (s0 + s1), (s0 + s1) * s2 / (s0 + s1 + s2)]
+        Ds, Ls = [], [s0 * s1 / (s0 + s1), s1 * s2 / (s1 + s2)]
         for j in range(2):
             ed = slots[j]
             e = ed["e"]

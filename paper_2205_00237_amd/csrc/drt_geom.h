@@ -684,12 +684,15 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
     a = cx<G>(sc_ * cp_, sc_ * sp_);
     if constexpr (POL) a = a * gam;   // the tile keeps the field: the two patterns' projection
   } else if constexpr (DP == -2) {
-    // two edges: UTD for successive edges (non-slope), the second edge seeing the first
-    // edge's field as from the unfolded distance s0 + s1 (exact for parallel edges);
-    // spreading 1 / sqrt(s0 s1 s2 (s0 + s1 + s2))
+    // two edges: UTD for successive edges (non-slope).  The first edge's field reaches the
+    // second as an astigmatic wave with a caustic on the first edge (radius s1) and one at
+    // the source's distance s0 + s1; the Kouyoumjian-Pathak distance parameter of that wave
+    // is s1 s2 sin^2 b / (s1 + s2) at the second edge (s0 s1 sin^2 b / (s0 + s1) at the
+    // first), and the spreading is 1 / sqrt(s0 s1 s2 (s0 + s1 + s2)); exact for parallel
+    // edges
     const G k = G(2) * pi / lam;
     const F Lsum = len[0] + len[1] + len[2];
-    const F Lpar[2] = {len[0] * len[1] / (len[0] + len[1]), (len[0] + len[1]) * len[2] / Lsum};
+    const F Lpar[2] = {len[0] * len[1] / (len[0] + len[1]), len[1] * len[2] / (len[1] + len[2])};
     Cx<G> Dprod = cx<G>(G(1), G(0));
 #pragma unroll
     for (int j = 0; j < 2; ++j) {

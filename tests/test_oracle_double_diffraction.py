@@ -5,9 +5,11 @@ extension of Sec. III-B:
   (the path stays in that horizontal plane); agreement with the Fermat snapshot re-tracer
   (an independent minimisation on the moved polyhedra) on moving, rotating boxes; Keller's
   law at both edges;
-* coefficient: the UTD product written out in the test from the single-edge coefficient of
-  em.py with the angles and distances computed here, for the parallel-edge geometry in
-  which the successive-edge caustic distances are exact;
+* coefficient: continuity of the total field where either edge's shadow boundary switches
+  a singly diffracted ray off (the doubly diffracted ray must cancel the jump, which fixes
+  both distance parameters and the spreading); the UTD product written out in the test from
+  the single-edge coefficient of em.py with the angles and distances computed here, for
+  the parallel-edge geometry in which the successive-edge caustic distances are exact;
 * kinematics: velocities and accelerations of both points against finite differences of the
   re-solved points; Doppler against -(f_c/c) dL/dt;
 * tracing: the path over two screen edges exists with its closed-form length and is
@@ -61,9 +63,54 @@ def test_parallel_edges_closed_form():
     phi2 = math.atan2(-10.0, 4.5) % (2 * math.pi)           # towards Rx (+10, -4.5)
     D1 = utd_coefficient(np.array(phi1), np.array(phi_p1), np.array(1.0), 2.0, k, np.array(s0 * s1 / (s0 + s1)), 0)
     D2 = utd_coefficient(np.array(phi2), np.array(phi_p2), np.array(1.0), 2.0, k,
-                         np.array((s0 + s1) * s2 / (s0 + s1 + s2)), 0)
+                         np.array(s1 * s2 / (s1 + s2)), 0)
     want = LAM / (4 * math.pi) * D1 * D2 / math.sqrt(s0 * s1 * s2 * (s0 + s1 + s2))
     assert abs(ex["gain"][0, 0] - want) < 1e-12 * abs(want)
+
+
+def _two_edge_fields(tx, rx, pol):
+    """Screens x = 10 (edge at y = 2, face towards +y) and x = 20 (edge at y = -8, face
+    towards -y), both vertical half-planes: fields a exp(-j k L) of the rays over edge 1,
+    over edge 2 and over both."""
+    b = SceneBuilder()
+    e1 = b.add_edge(0, (10, 2, 0), (0, 0, 1), (0, 1, 0), (-1, 0, 0), 2.0)
+    e2 = b.add_edge(0, (20, -8, 0), (0, 0, 1), (0, -1, 0), (-1, 0, 0), 2.0)
+    b.add_ray((KIND_D,), (e1,), (pol,))
+    b.add_ray((KIND_D,), (e2,), (pol,))
+    b.add_ray((KIND_D, KIND_D), (e1, e2), (pol, pol))
+    ex = oracle.extrapolate(b.build(tx_p=tx, rx_p=rx), np.array([0.0]), F_C)
+    assert ex["valid"].all()
+    return ex["gain"][:, 0] * np.exp(-2j * math.pi * F_C / C0 * ex["L"][:, 0])
+
+
+def test_double_diffraction_continuous_at_both_shadow_boundaries():
+    """Edge 2's shadow boundary for the field of edge 1 (RX on the line from Q1 through Q2:
+    in plan view x = 30, y = -18) switches the ray over edge 1 alone off; edge 1's shadow
+    boundary for the source (TX on the line from Q2 through Q1: x = 0, y = 12) switches the
+    ray over edge 2 alone off.  In both cases the ray over both edges must cancel the jump:
+    the residual, after removing the linear variation, is set by the other edge's own
+    transition (a few 1e-3 of the jump here), while a distance parameter of the second edge
+    taken as from a point source at the unfolded distance s0 + s1 leaves about 13%."""
+    for pol in (0, 1):
+        for tz, rz in ((1.5, 1.5), (9.0, -4.0)):
+            cases = (
+                # (moving terminal, position at parameter m, index of the ray that switches off,
+                #  sign of m on its lit side)
+                (lambda m: ((0, 6, tz), (30, -18 + m, rz)), 0, +1),
+                (lambda m: ((0, 12 + m, tz), (30, -30, rz)), 1, -1),
+            )
+            for place, off, lit in cases:
+                d = 1e-6
+                U, single = [], None
+                for m in (-3, -1, 1, 3):
+                    tx, rx = place(m * d)
+                    E = _two_edge_fields(tx, rx, pol)
+                    on = (m > 0) == (lit > 0)
+                    U.append(E[2] + (E[off] if on else 0))
+                    if on and abs(m) == 1:
+                        single = E[off]
+                jump = (U[2] - U[1]) - 0.5 * ((U[3] - U[2]) + (U[1] - U[0]))
+                assert abs(jump) < 5e-3 * abs(single), (pol, tz, off, abs(jump) / abs(single))
 
 
 def test_points_match_the_fermat_retracer_and_keller():
@@ -175,7 +222,7 @@ def test_path_along_a_face_reads_grazing_angles():
     k = 2 * math.pi / LAM
     s0, s1, s2 = math.hypot(5, 5), 2.0, math.hypot(6, 4)
     angles = [(0.0, 1.25 * math.pi), (math.atan2(-4.0, -6.0) % (2 * math.pi), 0.0)]   # (phi, phi') per edge
-    Ls = [s0 * s1 / (s0 + s1), (s0 + s1) * s2 / (s0 + s1 + s2)]
+    Ls = [s0 * s1 / (s0 + s1), s1 * s2 / (s1 + s2)]
     rng = np.random.default_rng(11)
     want = []
     for pol in (0, 1):

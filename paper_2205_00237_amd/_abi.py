@@ -21,6 +21,7 @@ DRT_E_NOTFOUND = -5
 DRT_E_BUSY = -6
 DRT_E_DEVICE = -7
 DRT_E_INCONSISTENT = -8
+DRT_E_CANCELLED = -9
 
 DRT_FP64, DRT_SPLIT, DRT_NAIVE32 = 0, 1, 2
 
@@ -28,7 +29,6 @@ EXPORTS = ("drt_create", "drt_destroy", "drt_load_scene", "drt_unload_scene", "d
            "drt_power_profiles", "drt_trace", "drt_scene_rays", "drt_segments", "drt_cfr_nufft",
            "drt_cfr", "drt_submit", "drt_poll", "drt_now", "drt_strerror", "drt_last_error",
            "drt_profile_enable", "drt_profile_read", "drt_serving_stats_get")
-PROBE_EXPORTS = ("drt_probe_mfma_f32_16x16x4", "drt_probe_mfma_f16_16x16x32", "drt_probe_sincos_rev")
 KERNELS = ("pose", "geom", "cfr", "reduce")
 
 _dp = C.POINTER(C.c_double)
@@ -113,7 +113,7 @@ class ReqStat(C.Structure):
 
 class ServingStats(C.Structure):
     _fields_ = [("batches", C.c_int64), ("batched_requests", C.c_int64), ("single_launches", C.c_int64),
-                ("max_batch", C.c_int32), ("slots", C.c_int32)]
+                ("max_batch", C.c_int32), ("slots", C.c_int32), ("failed_nomem", C.c_int64)]
 
 
 class Profile(C.Structure):
@@ -159,9 +159,6 @@ def _load():
         "drt_last_error": (C.c_char_p, []),
         "drt_profile_enable": (C.c_int, [vp, C.c_int]),
         "drt_profile_read": (C.c_int, [vp, C.POINTER(Profile), C.c_int]),
-        "drt_probe_mfma_f32_16x16x4": (C.c_int, [vp, vp, vp]),
-        "drt_probe_sincos_rev": (C.c_int, [vp, C.c_int32, vp, vp]),
-        "drt_probe_mfma_f16_16x16x32": (C.c_int, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -379,17 +376,3 @@ def drt_profile_read(ctx, reset=True):
     _check(LIB.drt_profile_read(ctx, C.byref(p), int(bool(reset))), "drt_profile_read")
     return {k: (p.ms[i], p.launches[i]) for i, k in enumerate(KERNELS)}
 
-
-def drt_probe_mfma_f32_16x16x4(A_ptr, B_ptr, D_ptr):
-    _check(LIB.drt_probe_mfma_f32_16x16x4(C.c_void_p(int(A_ptr)), C.c_void_p(int(B_ptr)),
-                                          C.c_void_p(int(D_ptr))), "drt_probe_mfma_f32_16x16x4")
-
-
-def drt_probe_sincos_rev(x_ptr, n, s_ptr, c_ptr):
-    _check(LIB.drt_probe_sincos_rev(C.c_void_p(int(x_ptr)), int(n), C.c_void_p(int(s_ptr)),
-                                    C.c_void_p(int(c_ptr))), "drt_probe_sincos_rev")
-
-
-def drt_probe_mfma_f16_16x16x32(A_ptr, B_ptr, D_ptr):
-    _check(LIB.drt_probe_mfma_f16_16x16x32(C.c_void_p(int(A_ptr)), C.c_void_p(int(B_ptr)),
-                                           C.c_void_p(int(D_ptr))), "drt_probe_mfma_f16_16x16x32")

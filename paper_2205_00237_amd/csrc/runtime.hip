@@ -678,8 +678,47 @@ static void finish(drt_ctx* c, Slot_& sl, int state) {
 // A request runs in a graph batch when its ray sum is the binary16 matrix-core one.
 static bool batchable(drt_ctx* c, const Request* q, CfrPlan* p) {
   if (q->r.precision != DRT_SPLIT || q->scene->view.polar) return false;   // batch kernels: scalar model
+  if (q->r.n_rays == 0) return false;                                       // served by a zero fill
   *p = plan(c, *q->scene, q->r.n_rays, q->r.tg.n_steps, &q->r.fg, q->r.precision);
   return p->a.path == CFR_MFMA16 && cfr_shape(p->a.MT, p->a.NT) >= 0;
+}
+
+// Give back device memory that no running batch uses: the arenas of idle slots other than
+// `keep` and, with `callers`, the per-stream scratch buffers of drt_extrapolate / drt_cfr
+// and the other stream-ordered calls.  Those streams belong to the callers, so the wait
+// before freeing them is device-wide; a caller inside one of those calls holds scratch_mu,
+// and then its buffer is left alone this time.
+static void reclaim(drt_ctx* c, Slot_* keep, bool callers) {
+  for (auto& sl : c->slots)
+    if (&sl != keep && sl.reqs.empty() && sl.scratch.buf.p) {
+      (void)hipStreamSynchronize(sl.stream);
+      dev_free(c, sl.scratch.buf);
+    }
+  if (!callers) return;
+  std::unique_lock<std::mutex> g(c->scratch_mu, std::try_to_lock);
+  if (!g.owns_lock() || c->scratch.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->scratch) dev_free(c, kv.second.buf);
+  c->scratch.clear();
+}
+
+// The queue head needs `need` bytes of arena and the budget of slot `sl` is smaller.  Idle
+// arenas are reclaimed at once; while batches run, the head waits for them (false: no
+// progress); with nothing running, caller scratch is reclaimed too, and a head that still
+// does not fit fails with DRT_E_NOMEM so that the requests behind it can go (true).
+static bool head_blocked(drt_ctx* c, Slot_& sl, Request* head, size_t need) {
+  bool busy = false;
+  for (auto& s : c->slots) busy = busy || !s.reqs.empty();
+  reclaim(c, &sl, !busy);
+  if (busy) return false;
+  const size_t budget = (c->cap > c->used.load() ? c->cap - c->used.load() : 0) + sl.scratch.buf.bytes;
+  if (need <= budget) return true;   // fits now: the caller's loop admits it next
+  c->queue.pop_front();
+  head->state = DRT_E_NOMEM;
+  head->t_admit = head->t_done = drt_now_impl();
+  head->scene->inflight--;
+  c->stats.failed_nomem++;
+  return true;
 }
 
 // Admit the queue head and, when it is batchable, the batchable requests behind it (FIFO)
@@ -696,8 +735,10 @@ static bool launch_next(drt_ctx* c, Slot_& sl) {
   double work = 0;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   if (!batch) {
-    if (head->footprint > budget) return false;
-    take.push_back({head, plan(c, *head->scene, head->r.n_rays, head->r.tg.n_steps, &head->r.fg, head->r.precision)});
+    if (head->footprint > budget) return head_blocked(c, sl, head, head->footprint);
+    CfrPlan p{};
+    if (head->r.n_rays > 0) p = plan(c, *head->scene, head->r.n_rays, head->r.tg.n_steps, &head->r.fg, head->r.precision);
+    take.push_back({head, p});
     arena = head->footprint;
   } else {
     for (size_t i = 0; i < c->queue.size() && take.size() < size_t(kMaxBatch); ++i) {
@@ -708,7 +749,7 @@ static bool launch_next(drt_ctx* c, Slot_& sl) {
       double w = double(q->r.n_rays) * q->r.tg.n_steps * q->r.fg.n_sub;
       if (i > 0 && work + w > c->batch_samples) break;   // the first request always fits
       if (arena + al(p.total) > budget) {
-        if (i == 0) return false;
+        if (i == 0) return head_blocked(c, sl, head, al(p.total));
         break;
       }
       take.push_back({q, p});
@@ -728,8 +769,14 @@ static bool launch_next(drt_ctx* c, Slot_& sl) {
   int st = ensure_scratch(c, sl.scratch, arena, sl.stream, budget);
   if (st == DRT_OK && !batch) {
     Request* q = take[0].first;
-    st = run_cfr(nullptr, *q->scene, q->r.n_rays, &q->r.tg, &q->r.fg, q->r.precision, q->r.H, take[0].second,
-                 sl.scratch.buf.p, sl.stream);
+    if (q->r.n_rays == 0) {   // no rays: H is zero, as drt_cfr writes it
+      const size_t cb = q->r.precision == DRT_FP64 ? 16 : 8;
+      if (launch_zero(q->r.H, size_t(q->r.tg.n_steps) * q->r.fg.n_sub * cb, sl.stream) != hipSuccess)
+        st = fail(DRT_E_DEVICE, "zero fill");
+    } else {
+      st = run_cfr(nullptr, *q->scene, q->r.n_rays, &q->r.tg, &q->r.fg, q->r.precision, q->r.H, take[0].second,
+                   sl.scratch.buf.p, sl.stream);
+    }
     c->stats.single_launches++;
   } else if (st == DRT_OK) {
     BatchDesc* h = sl.h_desc;
@@ -796,6 +843,17 @@ static void serve_loop(drt_ctx* c) {
         progress = true;
       }
     }
+    // a context being destroyed starts nothing more: queued requests are cancelled
+    if (c->stop && !c->queue.empty()) {
+      const double now = drt_now_impl();
+      for (Request* q : c->queue) {
+        q->state = DRT_E_CANCELLED;
+        q->t_done = now;
+        q->scene->inflight--;
+      }
+      c->queue.clear();
+      progress = true;
+    }
     // admissions: while a slot is free, batch the queue head with what waits behind it
     while (!c->queue.empty()) {
       Slot_* free_slot = nullptr;
@@ -837,6 +895,7 @@ const char* drt_strerror(int status) {
     case DRT_E_BUSY: return "scene busy";
     case DRT_E_DEVICE: return "HIP runtime error";
     case DRT_E_INCONSISTENT: return "t0 interaction points inconsistent";
+    case DRT_E_CANCELLED: return "request cancelled: context destroyed";
     default: return "unknown status";
   }
 }
@@ -1621,9 +1680,8 @@ int drt_submit(drt_ctx* c, const drt_request* r, uint64_t* ticket) {
   q->r = *r;
   q->scene = s;
   q->t_arrive = now;
-  q->footprint = (r->tg.n_steps > 0 && r->fg.n_sub > 0 && r->n_rays > 0)
-                     ? plan(c, *s, r->n_rays, r->tg.n_steps, &r->fg, r->precision).total
-                     : 0;
+  const bool empty = r->tg.n_steps == 0 || r->fg.n_sub == 0;   // nothing to write
+  q->footprint = (!empty && r->n_rays > 0) ? plan(c, *s, r->n_rays, r->tg.n_steps, &r->fg, r->precision).total : 0;
   size_t resident = 0;
   for (auto& kv : c->scenes) resident += kv.second->bytes;
   if (q->footprint + resident > c->cap)
@@ -1632,7 +1690,7 @@ int drt_submit(drt_ctx* c, const drt_request* r, uint64_t* ticket) {
   q->ticket = c->next_ticket++;
   *ticket = q->ticket;
   s->inflight++;
-  if (q->footprint == 0) {   // nothing to compute
+  if (empty) {
     q->state = 2;
     q->t_admit = q->t_done = now;
     s->inflight--;

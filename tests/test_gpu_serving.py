@@ -63,14 +63,17 @@ def test_alone_equals_in_mix(ctx):
             K = 4096                    # ray sum off the matrix cores: served alone
         reqs.append((sid, R, scenes.TimeGrid(1e-3, T), scenes.FreqGrid(float((28e9, 60e9)[i % 2]), 400e6, K),
                      prec))
+    reqs.append((sid2, 0, scenes.TimeGrid(1e-3, 40), scenes.FreqGrid(28e9, 400e6, 256), 1))   # no rays: H = 0
     alone = []
     for sid, R, tg, fg, prec in reqs:
         alone.append(ctx.cfr(sid, tg, fg, prec, n_rays=R).clone())
     torch.cuda.synchronize()
     before = ctx.serving_stats()
-    n_split = sum(1 for r in reqs if r[4] == 1 and r[3].n_sub <= 2048)
+    n_split = sum(1 for r in reqs if r[4] == 1 and r[3].n_sub <= 2048 and r[1] > 0)
     for burst in range(3):
-        outs = [torch.zeros_like(a) for a in alone]
+        outs = [torch.empty_like(a) for a in alone]
+        for o in outs:
+            o.view(torch.float32).fill_(7.0)      # every served H must be written, zeros included
         tickets = [ctx.submit(sid, R, tg, fg, H, precision=prec) for (sid, R, tg, fg, prec), H in zip(reqs, outs)]
         done = _wait(ctx, tickets)
         for i, (t, a, o) in enumerate(zip(tickets, alone, outs)):
@@ -153,3 +156,48 @@ def test_admission_and_errors(ctx):
             small.unload_scene(sid)
     finally:
         small.close()
+
+
+def test_blocked_head_reclaims_caller_scratch(ctx):
+    """Under a small cap, a drt_cfr on a side stream leaves a large scratch buffer behind; a
+    request that fits the cap minus the resident scene, but not the memory left beside that
+    buffer, must still complete (the buffer is given back), not wait forever."""
+    say("serving: blocked head, caller scratch reclaimed")
+    from paper_2205_00237_amd.drt import Context
+    s, _, fg = scenes.config1()
+    small = Context(0, hbm_cap_bytes=96 << 20)
+    try:
+        sid = small.load_scene(s)
+        side = torch.cuda.Stream()
+        big = scenes.TimeGrid(1e-4, 60000)            # ~50 MB of records and pose table
+        with torch.cuda.stream(side):
+            small.cfr(sid, big, fg, 1, stream=side)
+        side.synchronize()
+        tg = scenes.TimeGrid(1e-4, 50000)             # ~42 MB: fits 96 MB, not 96 MB - ~62 MB
+        rid = ctx.load_scene(s)                       # reference from an uncapped context
+        ref = ctx.cfr(rid, tg, fg, 1).clone()
+        torch.cuda.synchronize()
+        ctx.unload_scene(rid)
+        H = torch.empty_like(ref)
+        t = small.submit(sid, 25, tg, fg, H)
+        st = _wait(small, [t], timeout=30.0)[t]
+        say(f"  state {st[0]}, stats {small.serving_stats()}")
+        assert st[0] == 2
+        assert torch.equal(H.view(torch.float32), ref.view(torch.float32))
+    finally:
+        small.close()
+
+
+def test_destroy_with_a_queue_returns():
+    """Destroying a context with requests still queued cancels them and returns."""
+    say("serving: destroy with a queue")
+    from paper_2205_00237_amd.drt import Context
+    s, tg, fg = scenes.config2(seed=13)
+    c = Context(0)
+    sid = c.load_scene(s)
+    H = torch.empty((tg.n_steps, fg.n_sub), dtype=torch.complex64, device="cuda")
+    for _ in range(40):
+        c.submit(sid, len(s["ray_nint"]), tg, fg, H)
+    t0 = time.time()
+    c.close()
+    assert time.time() - t0 < 20.0

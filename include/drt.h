@@ -45,7 +45,8 @@ enum drt_status {
   DRT_E_NOTFOUND = -5,     /* unknown scene id or ticket */
   DRT_E_BUSY = -6,         /* scene still referenced by requests in flight */
   DRT_E_DEVICE = -7,       /* a HIP runtime call failed */
-  DRT_E_INCONSISTENT = -8  /* ray_q0 disagrees with the t0 solve by more than 1e-6 m */
+  DRT_E_INCONSISTENT = -8, /* ray_q0 disagrees with the t0 solve by more than 1e-6 m */
+  DRT_E_CANCELLED = -9     /* a served request still queued when its context was destroyed */
 };
 
 /* Arithmetic of a call.  DRT_FP64: everything in binary64, gains and H complex128.
@@ -161,7 +162,8 @@ typedef struct {
   double t_arrive, t_admit, t_done;            /* seconds on the library's monotonic clock */
 } drt_req_stat;
 
-/* Create a context on HIP device `device`.  hbm_cap_bytes bounds the device memory the
+/* Create a context on HIP device `device` (library lifetime management; no passage of the
+ * paper defines it).  hbm_cap_bytes bounds the device memory the
  * context holds (resident scenes, scratch, in-flight requests); 0 = 90% of the device.
  * Three environment variables, read here, are tuning knobs: DRT_CFR_KERNEL (mfma16, the
  * default; mfma32; valu) picks the split ray-sum kernel, DRT_TARGET_WAVES (64 .. 2^24) the
@@ -170,7 +172,10 @@ typedef struct {
  * batch may hold; a malformed value fails the call with DRT_E_INVAL. */
 int drt_create(int device, uint64_t hbm_cap_bytes, drt_ctx **out);
 
-/* Destroy a context: waits for in-flight work, frees every scene and scratch buffer. */
+/* Destroy a context: waits for the work already started (served batches, calls on caller
+ * streams), cancels served requests still queued (DRT_E_CANCELLED; their H is not
+ * written), frees every scene and scratch buffer.  Not a call of the paper's method: the
+ * library's own lifetime management, as are drt_create and drt_strerror. */
 int drt_destroy(drt_ctx *ctx);
 
 /* Validate, pack and upload a scene (Sec. II's dynamic environment database plus the t0
@@ -317,7 +322,9 @@ int drt_cfr(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_grid *t
 int drt_cfr_nufft(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_grid *tg,
                   const drt_freq_grid *fg, double eps, void *H, void *stream);
 
-/* Serving: enqueue one channel-prediction request.  Non-blocking.  DRT_E_ADMISSION if
+/* Serving: enqueue one channel-prediction request (Sec. IV-D: the predicted channel is to be
+ * served ahead of time to the network that asks for it; a request is the H(t, f) of
+ * drt_cfr over its own horizon, band and rays).  Non-blocking.  DRT_E_ADMISSION if
  * its device footprint alone exceeds the cap; otherwise it waits in the queue until a
  * batch slot and memory free up.  A worker thread keeps up to four batches in flight, each
  * on its own stream: a free slot takes the queue head and, FIFO, the split-precision
@@ -330,8 +337,11 @@ int drt_cfr_nufft(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_g
  * until drt_poll reports done or an error. */
 int drt_submit(drt_ctx *ctx, const drt_request *req, uint64_t *ticket);
 
-/* Non-blocking status of a ticket; a ticket reported done or failed is forgotten
- * afterwards (DRT_E_NOTFOUND on the next poll). */
+/* Non-blocking status of a ticket (Sec. IV-D, the serving side of channel prediction); a
+ * ticket reported done or failed is forgotten afterwards (DRT_E_NOTFOUND on the next poll).
+ * A request whose arena cannot fit in the HBM cap even with nothing else running fails with
+ * DRT_E_NOMEM (memory held by idle batch slots and by the per-stream scratch of the calls
+ * above is given back first), so that the requests queued behind it proceed. */
 int drt_poll(drt_ctx *ctx, uint64_t ticket, drt_req_stat *stat);
 
 /* Serving counters since the context was created. */
@@ -341,6 +351,7 @@ typedef struct {
   int64_t single_launches;    /* requests served alone on a slot */
   int32_t max_batch;          /* largest batch so far */
   int32_t slots;              /* batches that can be in flight at once (0 before the first submit) */
+  int64_t failed_nomem;       /* requests failed with DRT_E_NOMEM: no room even with nothing running */
 } drt_serving_stats;
 int drt_serving_stats_get(drt_ctx *ctx, drt_serving_stats *out);
 
@@ -361,6 +372,8 @@ typedef struct {
 int drt_profile_enable(drt_ctx *ctx, int on);
 int drt_profile_read(drt_ctx *ctx, drt_profile *out, int reset);
 
+/* Text of a status code, and the detail of the calling thread's last error (error
+ * reporting of the library itself; no passage of the paper defines it). */
 const char *drt_strerror(int status);
 const char *drt_last_error(void);
 

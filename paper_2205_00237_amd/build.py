@@ -6,7 +6,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdrt.so")
-SOURCES = ("kernels.hip", "runtime.hip", "trace.hip", "nufft.hip", "probe.hip")
+SOURCES = ("kernels.hip", "runtime.hip", "trace.hip", "nufft.hip")
+# test-only hardware probes (MFMA lane layouts, v_sin/v_cos): their own library under tests/
+PROBE_SRC = os.path.join(os.path.dirname(HERE), "tests", "probe", "probe.hip")
+PROBE_OUT = os.path.join(os.path.dirname(PROBE_SRC), "libdrt_probe.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -18,8 +21,12 @@ FLAGS = [
 
 
 def build(verbose=True, jobs=2):
-    """Compile every HIP source to an object in parallel, then link libdrt.so."""
+    """Compile every HIP source to an object in parallel, then link libdrt.so; the test-only
+    probe library is compiled alongside."""
     objs, procs = [], []
+    probe_tmp = PROBE_OUT + ".tmp"
+    probe_cmd = [HIPCC] + FLAGS + [PROBE_SRC, "-o", probe_tmp]
+    procs.append((probe_cmd, subprocess.Popen(probe_cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     for src in SOURCES:
         obj = os.path.join(SRC, src.replace(".hip", ".o"))
         cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", os.path.join(SRC, src), "-o", obj]
@@ -33,6 +40,7 @@ def build(verbose=True, jobs=2):
             raise RuntimeError(f"hipcc failed: {' '.join(cmd)}\n{text}")
         if verbose and text.strip():
             print(text, file=sys.stderr)
+    os.replace(probe_tmp, PROBE_OUT)
     tmp = OUT + ".tmp"
     link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(link, capture_output=True, text=True)

@@ -2,7 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/drt.h"
-#include "../../include/drt_probe.h"
+#include "drt_probe.h"
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 

@@ -32,11 +32,24 @@ def test_library_exports_every_declared_symbol():
     from paper_2205_00237_amd import _abi
     lib = ctypes.CDLL(_abi.LIB_PATH)
     every = _declared(HEADERS)
-    assert len(every) > len(_declared())
     for n in every:
         assert hasattr(lib, n), n
-    assert set(_abi.EXPORTS) == set(_declared())
-    assert set(_abi.EXPORTS) | set(_abi.PROBE_EXPORTS) == set(every)
+    assert set(_abi.EXPORTS) == set(every)
+    assert not any(n.startswith("drt_probe") for n in every)
+
+
+def test_probe_library_is_separate():
+    """The hardware probes live in a test-only library with its own header under tests/."""
+    import probe
+    hdr = os.path.join(ROOT, "tests", "probe", "drt_probe.h")
+    assert set(_declared((hdr,))) == set(probe.EXPORTS)
+    lib = ctypes.CDLL(probe.PATH)
+    for n in probe.EXPORTS:
+        assert hasattr(lib, n), n
+    from paper_2205_00237_amd import _abi
+    main = ctypes.CDLL(_abi.LIB_PATH)
+    for n in probe.EXPORTS:
+        assert not hasattr(main, n), n
 
 
 def test_host_only_helpers():

@@ -55,8 +55,8 @@ def _errors(out, ref, cols, H, Href, f_c):
         "L_m": float(np.abs(L - ref["L"])[v].max()),
         "tau_s": float(np.abs(L - ref["L"])[v].max() / C0),
         "doppler_hz": float(np.abs(dop - ref["dop"])[v].max()),
-        "gain_rel": float((np.abs(np.abs(g) - np.abs(gr)) / np.abs(gr))[big].max()),
-        "gain_arg_rad": float(np.abs(np.angle(g * np.conj(gr)))[big].max()),
+        "gain_rel": float((np.abs(np.abs(g[big]) - np.abs(gr[big])) / np.abs(gr[big])).max()),
+        "gain_arg_rad": float(np.abs(np.angle(g[big] * np.conj(gr[big]))).max()),
         "H_all": float(np.abs(H - Href).max() / rms),
         "H_mag": float((np.abs(np.abs(H[m]) - np.abs(Href[m])) / np.abs(Href[m])).max()),
         "H_arg_rad": float(np.abs(np.angle(H[m] * np.conj(Href[m]))).max()),

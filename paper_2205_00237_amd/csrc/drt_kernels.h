@@ -1,4 +1,4 @@
-// Launchers of the gfx950 kernels (kernels.hip) used by the host runtime.
+// Launchers of the gfx950 kernels (kernels_*.hip) used by the host runtime.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,7 +10,7 @@
 namespace drt {
 
 enum GeomMode { GEOM_EXTRAP = 0, GEOM_ANCHOR = 1, GEOM_ANCHOR_MFMA = 2, GEOM_KIN = 3, GEOM_POWER = 4, GEOM_NUFFT = 5 };
-enum CfrPath { CFR_VALU = 0, CFR_MFMA = 1, CFR_MFMA16 = 2 };
+enum CfrPath { CFR_VALU = 0, CFR_MFMA = 1, CFR_MFMA16 = 2, CFR_MFMA64 = 3 };
 
 constexpr int kNK = 16;          // subcarriers walked by one lane from its phase anchor
 constexpr int kNK64 = 32;        // the same in binary64 (its phase anchor costs a binary64 sincos)
@@ -108,7 +108,8 @@ hipError_t launch_batch(int kind, const BatchDesc* d, int grid, hipStream_t st);
 
 size_t pose_bytes(int nb, int T, int prec);
 size_t record_bytes(int n_rays, int T, int prec);
-CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_waves, int prec, int split_path);
+CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_waves, int prec, int split_path,
+                 int fp64_path);
 
 hipError_t launch_pose(const DBody* bodies, int nb, int T, double dt, int prec, void* out, hipStream_t st);
 hipError_t launch_geom(const SceneView& sc, const RayClasses& rc, const void* pose, int T, double dt, double f_c,
@@ -149,6 +150,14 @@ __host__ __device__ inline void trace_decode(const TraceSig& g, int64_t c, int32
 // and c = a exp(-j 2 pi frac(f_c L / c)) (zero for an inconsistent chain).
 struct RecU {
   double x, cr, ci;
+};
+
+// Binary64 ray-sum record of the matrix-core path, instant-major [instant][ray]: |a|, the
+// first subcarrier's phase with arg a folded in, frac(f_0 L/c - arg a / 2 pi), the row-block
+// and subcarrier phases frac(B df L/c) and frac(df L/c) (cycles), and the column step
+// exp(-j 2 pi frac(16 df L/c)).
+struct RecM64 {
+  double amp, p0, pB, p1, fr, fi;
 };
 
 hipError_t launch_nufft(const RecU* rec, int R, int T, int K, int M, int w, double beta, double2* tw,

@@ -143,6 +143,7 @@ struct drt_ctx {
   int target_waves = 16384;
   double batch_samples = 4e9;                // work cap of one serving batch (DRT_BATCH_SAMPLES)
   int split_path = CFR_MFMA16;               // ray-sum kernel of DRT_SPLIT (DRT_CFR_KERNEL)
+  int fp64_path = CFR_VALU;                  // ray-sum kernel of DRT_FP64 (DRT_FP64_KERNEL)
 
   // kernel timing
   struct ProfRec { int kernel, n; hipEvent_t a, b; };   // n kernels back to back between a and b
@@ -514,7 +515,7 @@ static CfrPlan plan(drt_ctx* c, const Scene& s, int n_rays, int T, const drt_fre
   int K = fg->n_sub;
   double df = fg->bandwidth / K;
   double f0 = fg->f_c - double(K / 2) * df;
-  p.a = plan_cfr(n_rays, T, K, f0, df, c->target_waves, prec, c->split_path);
+  p.a = plan_cfr(n_rays, T, K, f0, df, c->target_waves, prec, c->split_path, c->fp64_path);
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   size_t cbytes = prec == DRT_FP64 ? 16 : 8;
   p.pose_off = 0;
@@ -919,6 +920,13 @@ int drt_create(int device, uint64_t hbm_cap_bytes, drt_ctx** out) {
     else if (!std::strcmp(k, "mfma32")) c->split_path = CFR_MFMA;
     else if (!std::strcmp(k, "mfma16")) c->split_path = CFR_MFMA16;
     else return fail(DRT_E_INVAL, "DRT_CFR_KERNEL=%s: expected valu, mfma32 or mfma16", k);
+  }
+  // comparison knob: which ray-sum kernel DRT_FP64 uses (the subcarrier walk on the vector
+  // ALU, or the split path's GEMM factorisation on the binary64 matrix cores)
+  if (const char* k = std::getenv("DRT_FP64_KERNEL")) {
+    if (!std::strcmp(k, "valu")) c->fp64_path = CFR_VALU;
+    else if (!std::strcmp(k, "mfma64")) c->fp64_path = CFR_MFMA64;
+    else return fail(DRT_E_INVAL, "DRT_FP64_KERNEL=%s: expected valu or mfma64", k);
   }
   // tuning knob: waves the ray sum aims for (sets the number of ray groups per instant)
   if (const char* w = std::getenv("DRT_TARGET_WAVES")) {

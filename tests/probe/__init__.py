@@ -5,7 +5,8 @@ import ctypes as C
 import os
 
 PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdrt_probe.so")
-EXPORTS = ("drt_probe_mfma_f32_16x16x4", "drt_probe_mfma_f16_16x16x32", "drt_probe_sincos_rev")
+EXPORTS = ("drt_probe_mfma_f32_16x16x4", "drt_probe_mfma_f16_16x16x32", "drt_probe_mfma_f64_16x16x4",
+           "drt_probe_sincos_rev")
 
 
 def load():
@@ -15,6 +16,7 @@ def load():
     vp = C.c_void_p
     for name, args in (("drt_probe_mfma_f32_16x16x4", [vp, vp, vp]),
                        ("drt_probe_mfma_f16_16x16x32", [vp, vp, vp]),
+                       ("drt_probe_mfma_f64_16x16x4", [vp, vp, vp]),
                        ("drt_probe_sincos_rev", [vp, C.c_int32, vp, vp])):
         f = getattr(lib, name)
         f.restype = C.c_int

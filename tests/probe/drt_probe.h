@@ -29,6 +29,11 @@ int drt_probe_mfma_f32_16x16x4(const float *A, const float *B, float *D);
  * hardware's lane layout. */
 int drt_probe_mfma_f16_16x16x32(const uint16_t *A, const uint16_t *B, float *D);
 
+/* v_mfma_f64_16x16x4_f64 on binary64 operands: lane l supplies A[l%16][l/16] and
+ * B[l/16][l%16] (as the binary32 instruction) and writes D[l/16+4*v][l%16] from accumulator
+ * element v (the binary64 accumulator interleaves its rows, unlike the binary32 one). */
+int drt_probe_mfma_f64_16x16x4(const double *A, const double *B, double *D);
+
 /* s[i] = v_sin_f32(x[i]), c[i] = v_cos_f32(x[i]): the hardware sine and cosine of an
  * angle given in revolutions (sin(2 pi x)).  n >= 0 elements. */
 int drt_probe_sincos_rev(const float *x, int32_t n, float *s, float *c);

@@ -29,6 +29,17 @@ __global__ __launch_bounds__(64) void k_probe_mfma16(const _Float16* A, const _F
   for (int v = 0; v < 4; ++v) D[(4 * (l / 16) + v) * 16 + l % 16] = acc[v];
 }
 
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(64) void k_probe_mfma64(const double* A, const double* B, double* D) {
+  int l = threadIdx.x;
+  double a = A[(l % 16) * 4 + l / 16];
+  double b = B[(l / 16) * 16 + l % 16];
+  doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  for (int v = 0; v < 4; ++v) D[(l / 16 + 4 * v) * 16 + l % 16] = acc[v];
+}
+
 __global__ __launch_bounds__(256) void k_probe_sincos(const float* x, int n, float* s, float* c) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -46,6 +57,13 @@ extern "C" int drt_probe_mfma_f32_16x16x4(const float* A, const float* B, float*
 extern "C" int drt_probe_mfma_f16_16x16x32(const uint16_t* A, const uint16_t* B, float* D) {
   if (!A || !B || !D) return DRT_E_INVAL;
   hipLaunchKernelGGL(k_probe_mfma16, dim3(1), dim3(64), 0, 0, (const _Float16*)A, (const _Float16*)B, D);
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) return DRT_E_DEVICE;
+  return DRT_OK;
+}
+
+extern "C" int drt_probe_mfma_f64_16x16x4(const double* A, const double* B, double* D) {
+  if (!A || !B || !D) return DRT_E_INVAL;
+  hipLaunchKernelGGL(k_probe_mfma64, dim3(1), dim3(64), 0, 0, A, B, D);
   if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) return DRT_E_DEVICE;
   return DRT_OK;
 }

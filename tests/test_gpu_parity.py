@@ -151,6 +151,9 @@ def test_config2_full_size(ctx):
     say("  oracle geometry at every instant ...")
     ref = oracle.extrapolate(s, np.arange(tg.n_steps) * tg.dt, fg.f_c)
     check_extrapolation(out, ref, 0, "config2", fg.f_c)
+    del out
+    say("  split-mode extrapolation at every instant ...")
+    check_extrapolation(ctx.extrapolate(sid, tg, fg.f_c, 1), ref, 1, "config2 split", fg.f_c)
     for prec in (0, 1):
         H = ctx.cfr(sid, tg, fg, prec).cpu().numpy().astype(np.complex128)[rows]
         e_all, e_mag, e_arg = h_errors(H, Href)
@@ -260,6 +263,38 @@ def test_split_ray_sum_kernels(kernel, monkeypatch):
             Gk = c.cfr(sid, tgk, fgk, 1, n_rays=700).cpu().numpy().astype(np.complex128)[[0, 33, 69]]
             e_all, e_mag, e_arg = h_errors(Gk, Hk)
             assert e_all <= 1e-4 and e_mag <= 1e-4 and e_arg <= 1e-3, (K, e_all, e_mag, e_arg)
+        c.unload_scene(sid)
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("kernel", ["valu", "mfma64"])
+def test_fp64_ray_sum_kernels(kernel, monkeypatch):
+    """Both binary64 ray sums (the subcarrier walk on the vector ALU; the split path's GEMM
+    factorisation on the binary64 matrix cores, used for 128 < K <= 1024) meet the binary64
+    tolerance |dH| <= 1e-6 rms on the urban workload's sampled instants and on ragged
+    subcarrier and ray counts (odd ray counts leave a ray pair half empty)."""
+    say(f"binary64 ray-sum kernel {kernel}")
+    from paper_2205_00237_amd.drt import Context
+    monkeypatch.setenv("DRT_FP64_KERNEL", kernel)
+    c = Context(0)
+    try:
+        s, tg, fg = scenes.config2()
+        sid = c.load_scene(s)
+        rows = np.array([0, 63, 64, 640, 999])
+        _, Href = oracle.run(s, tg, fg, t_index=rows)
+        H = c.cfr(sid, tg, fg, 0).cpu().numpy()[rows]
+        e_all, e_mag, e_arg = h_errors(H, Href)
+        say(f"  {kernel}: H errors all {e_all:.3g} mag {e_mag:.3g} arg {e_arg:.3g}")
+        assert e_all <= 1e-6
+        for K, R in ((129, 700), (200, 1), (256, 701), (300, 333), (512, 700), (513, 64), (1000, 699),
+                     (1024, 700), (2048, 300), (64, 700)):
+            fgk = scenes.FreqGrid(60e9, 400e6, K)
+            tgk = scenes.TimeGrid(1e-3, 70)
+            _, Hk = oracle.run(s, tgk, fgk, rays=np.arange(R), t_index=np.array([0, 33, 69]))
+            Gk = c.cfr(sid, tgk, fgk, 0, n_rays=R).cpu().numpy()[[0, 33, 69]]
+            e_all, e_mag, e_arg = h_errors(Gk, Hk)
+            assert e_all <= 1e-6, (K, R, e_all)
         c.unload_scene(sid)
     finally:
         c.close()

@@ -40,6 +40,21 @@ def test_mfma_f16_16x16x32_lane_layout():
     assert np.array_equal(dD.cpu().numpy(), A.astype(np.float32) @ B.astype(np.float32))
 
 
+def test_mfma_f64_16x16x4_lane_layout():
+    print("probe: mfma 16x16x4 f64 layout", flush=True)
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import probe
+    lib = probe.load()
+    rng = np.random.default_rng(3)
+    A = rng.normal(size=(16, 4))
+    B = rng.normal(size=(4, 16))
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dD = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    probe.call(lib, "drt_probe_mfma_f64_16x16x4", dA.data_ptr(), dB.data_ptr(), dD.data_ptr())
+    assert np.abs(dD.cpu().numpy() - A @ B).max() < 1e-14
+
+
 def test_hardware_sincos_on_revolutions():
     print("probe: v_sin/v_cos accuracy", flush=True)
     if not torch.cuda.is_available():

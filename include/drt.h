@@ -310,6 +310,20 @@ int drt_power_profiles(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_t
 int drt_cfr(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_grid *tg,
             const drt_freq_grid *fg, int32_t precision, void *H, void *stream);
 
+/* drt_cfr for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments, kernels and result
+ * as drt_cfr (bitwise), but the call's scratch (pose table, ray-sum records, partial sums)
+ * is one static device array of 256 MiB per GPU, set up by drt_create and held until the
+ * process ends; the call makes no hipMalloc, hipFree or other allocating call.  Errors:
+ * DRT_E_NOMEM when the call needs more than 256 MiB of scratch (about n_rays x n_steps x 32 B
+ * of records plus, for many rays, a few n_steps x n_sub x 8 B partial sums; the urban
+ * workload of 5000 rays x 1000 instants x 1024 subcarriers needs 201 MB); those of drt_cfr.
+ * Every call on one GPU, from any context or thread, uses that GPU's one array: calls on one
+ * stream are ordered and safe, calls that overlap on one GPU (other streams, other threads)
+ * race and give wrong results. */
+int drt_cfr_noalloc(drt_ctx *ctx, uint32_t scene, int32_t n_rays, const drt_time_grid *tg,
+                    const drt_freq_grid *fg, int32_t precision, void *H, void *stream);
+
 /* The same H as drt_cfr in binary64, by a type-1 non-uniform FFT along the subcarrier grid
  * (per instant about R w + 5 M log2 M operations instead of R K): per instant, each ray's
  * coefficient c = a exp(-j 2 pi frac(f_c L / c)) is spread at x = frac(df L / c) onto a

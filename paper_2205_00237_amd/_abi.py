@@ -27,7 +27,7 @@ DRT_FP64, DRT_SPLIT, DRT_NAIVE32 = 0, 1, 2
 
 EXPORTS = ("drt_create", "drt_destroy", "drt_load_scene", "drt_unload_scene", "drt_extrapolate",
            "drt_power_profiles", "drt_trace", "drt_scene_rays", "drt_segments", "drt_cfr_nufft",
-           "drt_cfr", "drt_submit", "drt_poll", "drt_now", "drt_strerror", "drt_last_error",
+           "drt_cfr", "drt_cfr_noalloc", "drt_submit", "drt_poll", "drt_now", "drt_strerror", "drt_last_error",
            "drt_profile_enable", "drt_profile_read", "drt_serving_stats_get")
 KERNELS = ("pose", "geom", "cfr", "reduce")
 
@@ -142,6 +142,8 @@ def _load():
                                       C.c_int32, C.POINTER(RayOut), vp]),
         "drt_cfr": (C.c_int, [vp, C.c_uint32, C.c_int32, C.POINTER(TimeGrid), C.POINTER(FreqGrid),
                               C.c_int32, vp, vp]),
+        "drt_cfr_noalloc": (C.c_int, [vp, C.c_uint32, C.c_int32, C.POINTER(TimeGrid), C.POINTER(FreqGrid),
+                                      C.c_int32, vp, vp]),
         "drt_cfr_nufft": (C.c_int, [vp, C.c_uint32, C.c_int32, C.POINTER(TimeGrid), C.POINTER(FreqGrid),
                                     C.c_double, vp, vp]),
         "drt_trace": (C.c_int, [vp, C.c_uint32, C.c_double, C.POINTER(TraceOpts), C.POINTER(C.c_uint32),
@@ -333,6 +335,13 @@ def drt_cfr(ctx, sid, n_rays, dt, n_steps, f_c, bandwidth, n_sub, precision, H_p
     fg = FreqGrid(float(f_c), float(bandwidth), int(n_sub))
     _check(LIB.drt_cfr(ctx, int(sid), int(n_rays), C.byref(tg), C.byref(fg), int(precision),
                        C.c_void_p(int(H_ptr)), C.c_void_p(int(stream))), "drt_cfr")
+
+
+def drt_cfr_noalloc(ctx, sid, n_rays, dt, n_steps, f_c, bandwidth, n_sub, precision, H_ptr, stream=0):
+    tg = TimeGrid(float(dt), int(n_steps))
+    fg = FreqGrid(float(f_c), float(bandwidth), int(n_sub))
+    _check(LIB.drt_cfr_noalloc(ctx, int(sid), int(n_rays), C.byref(tg), C.byref(fg), int(precision),
+                               C.c_void_p(int(H_ptr)), C.c_void_p(int(stream))), "drt_cfr_noalloc")
 
 
 def drt_cfr_nufft(ctx, sid, n_rays, dt, n_steps, f_c, bandwidth, n_sub, eps, H_ptr, stream=0):

@@ -169,6 +169,30 @@ static int set_device(drt_ctx* c) {
   return DRT_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// Scratch of drt_cfr_noalloc: one file-scope device array per GPU, held until the process
+// ends, for callers that cannot allocate.  Host code never passes the array's name to a
+// kernel (on the host it only names the symbol): its device address is looked up once per
+// device, in drt_create with that device current, and kept in noalloc_ptr.
+
+constexpr size_t kNoAllocBytes = size_t(256) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+static void* noalloc_ptr[kMaxDevices] = {};
+static std::mutex noalloc_mu;
+
+static int noalloc_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(DRT_E_INVAL, "device %d beyond %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> g(noalloc_mu);
+  if (noalloc_ptr[device]) return DRT_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(DRT_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+  noalloc_ptr[device] = p;
+  return DRT_OK;
+}
+
 static int dev_alloc(drt_ctx* c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (c->used.load() + bytes > c->cap)
@@ -911,6 +935,10 @@ int drt_create(int device, uint64_t hbm_cap_bytes, drt_ctx** out) {
   HIP_OK(hipSetDevice(device));
   size_t free_b = 0, total_b = 0;
   HIP_OK(hipMemGetInfo(&free_b, &total_b));
+  {
+    const int st = noalloc_setup(device);
+    if (st != DRT_OK) return st;
+  }
   auto c = std::make_unique<drt_ctx>();
   c->device = device;
   c->cap = hbm_cap_bytes ? hbm_cap_bytes : uint64_t(0.9 * double(total_b));
@@ -1594,6 +1622,33 @@ int drt_cfr(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg,
   Scratch& sc = c->scratch[hs];
   if ((st = ensure_scratch(c, sc, p.total, hs))) return st;
   return run_cfr(c, *s, n_rays, tg, fg, prec, H, p, sc.buf.p, hs);
+}
+
+int drt_cfr_noalloc(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg,
+                    const drt_freq_grid* fg, int32_t prec, void* H, void* stream) {
+  if (!c) return fail(DRT_E_INVAL, "null context");
+  Scene* s = find_scene(c, scene);
+  if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
+  int st;
+  if ((st = check_grid(tg, n_rays, *s)) || (st = check_fgrid(fg)) || (st = check_prec(prec, s))) return st;
+  if (tg->n_steps > 0 && fg->n_sub > 0 && !H) return fail(DRT_E_INVAL, "null H");
+  if ((st = set_device(c))) return st;
+  const int T = tg->n_steps, K = fg->n_sub;
+  if (T == 0 || K == 0) return DRT_OK;
+  hipStream_t hs = (hipStream_t)stream;
+  if (n_rays == 0) {
+    HIP_OK(launch_zero(H, size_t(T) * K * (prec == DRT_FP64 ? 16 : 8), hs));
+    return DRT_OK;
+  }
+  const CfrPlan p = plan(c, *s, n_rays, T, fg, prec);
+  if (p.total > kNoAllocBytes)
+    return fail(DRT_E_NOMEM, "drt_cfr_noalloc needs %zu bytes of scratch; its static scratch holds %zu",
+                p.total, kNoAllocBytes);
+  void* base = noalloc_ptr[c->device];
+  if (!base) return fail(DRT_E_DEVICE, "static scratch of device %d not set up", c->device);
+  // every scratch byte the kernels read is written first in the same call (pose table,
+  // records, partial sums): nothing to clear; no kernel timing (no event creation)
+  return run_cfr(nullptr, *s, n_rays, tg, fg, prec, H, p, base, hs);
 }
 
 int drt_cfr_nufft(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg, const drt_freq_grid* fg,

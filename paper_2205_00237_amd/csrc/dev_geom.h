@@ -151,9 +151,20 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   }
   F fc = F(f_c);
   using G = typename GainT<PREC>::type;
+  // a slot's pose rebuilt where the Doppler and the monitor need it, from the instant and the
+  // pose table; the empty asm statements keep the compiler from reusing (and so holding
+  // through the chain solve) the values computed when the slots were loaded
+  auto pose_of = [&](int i) {
+    F d = dtj;
+    int at = ray.body[i] * T + tq;
+    asm volatile("" : "+v"(d), "+v"(at));
+    const int b = ray.body[i];
+    const auto pe = pose[at];
+    return make_pose<F>(sc.bodies[b], d, F(pe.x), F(pe.y));
+  };
   RayResult<F, G> res = with_signature_in<F, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
-    return eval_ray<F, G, N, DP, SCAT, false, MODE == GEOM_EXTRAP || MODE == GEOM_POWER, POL>(sc, ray, sl, TX,
-                                                                                              VTX, RX, VRX, fc);
+    return eval_ray_with<F, G, N, DP, SCAT, false, MODE == GEOM_EXTRAP || MODE == GEOM_POWER, POL>(
+        sc, ray, sl, TX, VTX, RX, VRX, fc, pose_of);
   });
 
   if constexpr (MODE == GEOM_EXTRAP) {

@@ -583,9 +583,13 @@ DRT_HD CV3<G> diffract_field(CV3<G> E, V3<G> s_in, V3<G> s_out, V3<G> e, Cx<G> d
 // the validity monitor is evaluated too: every reflection point inside its wall's facet
 // (tested in the wall body's t0 frame, where the facet is fixed) with both neighbouring
 // vertices on the front side, and every diffraction point on its edge segment.
-template <class F, class G, int N, int DP, bool SCAT, bool KEEP_Q = false, bool MON = false, bool POL = false>
-DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot<F>* sl, V3<F> TX,
-                                V3<F> VTX, V3<F> RX, V3<F> VRX, F f_c) {
+// pose_of(i) gives the pose of slot i for the Doppler and the monitor: the slot's own copy,
+// or (on the device) one rebuilt from the instant and the pose table, so that the poses of
+// every slot need not stay in registers through the chain solve.
+template <class F, class G, int N, int DP, bool SCAT, bool KEEP_Q = false, bool MON = false, bool POL = false,
+          class PoseOf>
+DRT_HD RayResult<F, G> eval_ray_with(const SceneView& sc, const DRay& ray, const Slot<F>* sl, V3<F> TX,
+                                     V3<F> VTX, V3<F> RX, V3<F> VRX, F f_c, PoseOf&& pose_of) {
   RayResult<F, G> res;
   ChainOut<F> ch;
   if constexpr (SCAT) {
@@ -616,7 +620,7 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
   F dLdt = F(0);
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    V3<F> u = material_velocity(sl[i].pose, ch.Q[i]);
+    V3<F> u = material_velocity(pose_of(i), ch.Q[i]);
     dLdt += dot(kh[i], u - uprev);
     uprev = u;
   }
@@ -626,6 +630,36 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
   dir_angles(gv(kh[0]), res.aod_az, res.aod_el);
   dir_angles(gv(-kh[N]), res.aoa_az, res.aoa_el);
   res.L = L;
+  // validity monitor, evaluated while the points, vertices and poses are live and before
+  // the field code needs the registers (a scattering chain's monitor is its facing test)
+  bool in_bounds = true;
+  if constexpr (MON && !SCAT) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (i == DP || DP == -2) {
+        const DEdge& ed = sc.edges[ray.prim[i]];
+        const F zq = (DP == -2 && i == 1) ? ch.zQ2 : ch.zQ;
+        in_bounds = in_bounds && zq >= F(ed.zlo) && zq <= F(ed.zhi);
+        continue;
+      }
+      const V3<F> q = ch.Q[i], nn = sl[i].n;
+      in_bounds = in_bounds && dot(verts[i] - q, nn) >= F(0) && dot(verts[i + 2] - q, nn) >= F(0);
+      const DPlane& pl = sc.planes[ray.prim[i]];
+      if (pl.bounded) {
+        // back to the t0 frame of the wall's body: X0 = O0 + R(-theta)(X - O(t))
+        const Pose<F> ps = pose_of(i);
+        V3<F> x0 = q;
+        if (ps.moving) {
+          V3<F> w = q - ps.O;
+          V3<F> kw = cross(ps.k, w);
+          x0 = ps.O0 + (w - ps.s * kw + ps.c1 * cross(ps.k, kw));
+        }
+        const V3<F> d = x0 - ld3<F>(pl.c0);
+        const F su = dot(ld3<F>(pl.du), d), sv = dot(ld3<F>(pl.dv), d);
+        in_bounds = in_bounds && su >= F(0) && su <= F(1) && sv >= F(0) && sv <= F(1);
+      }
+    }
+  }
 
   const G pi = Consts<G>::pi;
   const G lam = G(Consts<F>::c0 / f_c);
@@ -761,41 +795,19 @@ DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot
   res.gain = a;
   res.ok = ok;
   res.degen = ch.degen;
-  res.in_bounds = ok;
-  if constexpr (MON && !SCAT) {
-    bool in = true;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      if (i == DP || DP == -2) {
-        const DEdge& ed = sc.edges[ray.prim[i]];
-        const F zq = (DP == -2 && i == 1) ? ch.zQ2 : ch.zQ;
-        in = in && zq >= F(ed.zlo) && zq <= F(ed.zhi);
-        continue;
-      }
-      const V3<F> q = ch.Q[i], nn = sl[i].n;
-      in = in && dot(verts[i] - q, nn) >= F(0) && dot(verts[i + 2] - q, nn) >= F(0);
-      const DPlane& pl = sc.planes[ray.prim[i]];
-      if (pl.bounded) {
-        // back to the t0 frame of the wall's body: X0 = O0 + R(-theta)(X - O(t))
-        const Pose<F>& ps = sl[i].pose;
-        V3<F> x0 = q;
-        if (ps.moving) {
-          V3<F> w = q - ps.O;
-          V3<F> kw = cross(ps.k, w);
-          x0 = ps.O0 + (w - ps.s * kw + ps.c1 * cross(ps.k, kw));
-        }
-        const V3<F> d = x0 - ld3<F>(pl.c0);
-        const F su = dot(ld3<F>(pl.du), d), sv = dot(ld3<F>(pl.dv), d);
-        in = in && su >= F(0) && su <= F(1) && sv >= F(0) && sv <= F(1);
-      }
-    }
-    res.in_bounds = ok && in;
-  }
+  res.in_bounds = ok && in_bounds;
   if constexpr (KEEP_Q) {
 #pragma unroll
     for (int i = 0; i < N; ++i) res.Q[i] = ch.Q[i];
   }
   return res;
+}
+
+template <class F, class G, int N, int DP, bool SCAT, bool KEEP_Q = false, bool MON = false, bool POL = false>
+DRT_HD RayResult<F, G> eval_ray(const SceneView& sc, const DRay& ray, const Slot<F>* sl, V3<F> TX,
+                                V3<F> VTX, V3<F> RX, V3<F> VRX, F f_c) {
+  return eval_ray_with<F, G, N, DP, SCAT, KEEP_Q, MON, POL>(sc, ray, sl, TX, VTX, RX, VRX, f_c,
+                                                            [&](int i) { return sl[i].pose; });
 }
 
 // Interaction points and path length of one ray with its slots moved as jets in time:

@@ -201,3 +201,31 @@ def test_destroy_with_a_queue_returns():
     t0 = time.time()
     c.close()
     assert time.time() - t0 < 20.0
+
+
+@pytest.mark.parametrize("K", [64, 200, 512, 1024, 2048])
+def test_served_request_against_oracle(ctx, K):
+    """One served split request per matrix tile shape of the binary16 ray sum (K = 64: 1 x 1,
+    200: 1 x 2, 512: 1 x 4, 1024: 2 x 4, 2048: 4 x 4 row x column tiles), its H compared with
+    the binary64 oracle on sampled instants to the split tolerance (|dH| <= 1e-4 rms, |H|
+    within 1e-4 and arg H within 1e-3 rad where |H_ref| >= 0.1 rms)."""
+    import oracle
+    say(f"serving vs oracle K={K}")
+    s, _, _ = scenes.config2(seed=11)
+    sid = ctx.load_scene(s)
+    R, tg, fg = 900, scenes.TimeGrid(1e-3, 130), scenes.FreqGrid(60e9, 400e6, K)
+    H = torch.empty((tg.n_steps, K), dtype=torch.complex64, device="cuda")
+    t = ctx.submit(sid, R, tg, fg, H)
+    st = _wait(ctx, [t])[t]
+    assert st[0] == 2
+    rows = np.array([0, 63, 64, 129])
+    _, Href = oracle.run(s, tg, fg, rays=np.arange(R), t_index=rows)
+    Hg = H.cpu().numpy().astype(np.complex128)[rows]
+    rms = np.sqrt(np.mean(np.abs(Href) ** 2))
+    m = np.abs(Href) >= 0.1 * rms
+    e_all = np.abs(Hg - Href).max() / rms
+    e_mag = (np.abs(np.abs(Hg[m]) - np.abs(Href[m])) / np.abs(Href[m])).max()
+    e_arg = np.abs(np.angle(Hg[m] * np.conj(Href[m]))).max()
+    say(f"  errors all {e_all:.3g} mag {e_mag:.3g} arg {e_arg:.3g}")
+    assert e_all <= 1e-4 and e_mag <= 1e-4 and e_arg <= 1e-3
+    ctx.unload_scene(sid)

@@ -1,6 +1,7 @@
 // Host runtime of libdrt: the C ABI of include/drt.h, the scene loader, scratch management
 // and the serving loop (continuous batching of channel-prediction requests).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <atomic>
@@ -33,6 +34,16 @@ using namespace drt_host;
     hipError_t e_ = (expr);                                                                \
     if (e_ != hipSuccess) return fail(DRT_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
+
+// A named range on the calling thread for a profiler's marker trace (rocprofv3
+// --marker-trace): every entry point that launches work, and every serving batch.  Without
+// a profiler attached each push and pop is a cheap no-op.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 double drt_now_impl() {
   using namespace std::chrono;
@@ -397,6 +408,7 @@ static int init_slots(drt_ctx* c) {
   c->slots.resize(kSlots);
   for (auto& sl : c->slots) {
     HIP_OK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+    roctxNameHipStream("drt serving slot", sl.stream);
     HIP_OK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
     HIP_OK(hipHostMalloc((void**)&sl.h_desc, sizeof(BatchDesc), hipHostMallocDefault));
     int st;
@@ -479,6 +491,7 @@ static bool head_blocked(drt_ctx* c, Slot_& sl, Request* head, size_t need) {
 // while the batch has room, its work stays under the cap and its arena fits in the HBM
 // budget.  Returns false when the head has to wait for memory.
 static bool launch_next(drt_ctx* c, Slot_& sl) {
+  Range range_("drt serving batch");
   Request* head = c->queue.front();
   CfrPlan hp;
   const bool batch = batchable(c, head, &hp);
@@ -582,6 +595,7 @@ static bool launch_next(drt_ctx* c, Slot_& sl) {
 
 static void serve_loop(drt_ctx* c) {
   (void)hipSetDevice(c->device);
+  roctxNameOsThread("drt serving loop");
   std::unique_lock<std::mutex> lk(c->mu);
   while (true) {
     bool progress = false;
@@ -758,6 +772,7 @@ static int make_resident(drt_ctx* c, std::unique_ptr<Scene> s, uint32_t* id) {
 }
 
 int drt_load_scene(drt_ctx* c, const drt_scene_desc* d, uint32_t* id) {
+  Range range_("drt_load_scene");
   if (!c || !id) return fail(DRT_E_INVAL, "null context or id");
   int st = set_device(c);
   if (st) return st;
@@ -827,6 +842,7 @@ static std::vector<TraceSig> trace_signatures(const drt_trace_opts& o, int np, i
 
 int drt_trace(drt_ctx* c, uint32_t scene, double t, const drt_trace_opts* o, uint32_t* new_scene,
               drt_trace_info* info) {
+  Range range_("drt_trace");
   if (!c || !o || !new_scene) return fail(DRT_E_INVAL, "null context, options or output");
   if (!std::isfinite(t)) return fail(DRT_E_INVAL, "trace instant must be finite");
   if (o->max_refl < 0 || o->max_refl > 3 || o->max_refl_diff < -1 || o->max_refl_diff > 2)
@@ -936,6 +952,7 @@ int drt_trace(drt_ctx* c, uint32_t scene, double t, const drt_trace_opts* o, uin
 int drt_segments(drt_ctx* c, uint32_t scene, const drt_time_grid* tg, double f_c, const drt_trace_opts* topts,
                  const drt_refresh_opts* ropts, int32_t max_segments, int32_t* seg_start, int32_t* seg_len,
                  uint32_t* seg_scene, int32_t* n_segments) {
+  Range range_("drt_segments");
   if (!c || !tg || !topts || !ropts || !n_segments || (max_segments > 0 && (!seg_start || !seg_len || !seg_scene)))
     return fail(DRT_E_INVAL, "null argument");
   if (tg->n_steps < 0 || !(tg->dt > 0) || !std::isfinite(tg->dt)) return fail(DRT_E_INVAL, "bad time grid");
@@ -1019,6 +1036,7 @@ int drt_scene_rays(drt_ctx* c, uint32_t scene, int32_t cap, int32_t* n_rays, uin
 
 int drt_extrapolate(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg, double f_c,
                     int32_t prec, const drt_ray_out* out, void* stream) {
+  Range range_("drt_extrapolate");
   if (!c || !out) return fail(DRT_E_INVAL, "null context or output");
   Scene* s = find_scene(c, scene);
   if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
@@ -1076,6 +1094,7 @@ int drt_extrapolate(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_g
 
 int drt_power_profiles(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg, double f_c,
                        int32_t prec, const drt_bins* bins, const drt_power_out* out, void* stream) {
+  Range range_("drt_power_profiles");
   if (!c || !bins || !out) return fail(DRT_E_INVAL, "null context, bins or output");
   Scene* s = find_scene(c, scene);
   if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
@@ -1130,6 +1149,7 @@ int drt_power_profiles(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_tim
 
 int drt_cfr(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg, const drt_freq_grid* fg,
             int32_t prec, void* H, void* stream) {
+  Range range_("drt_cfr");
   if (!c) return fail(DRT_E_INVAL, "null context");
   Scene* s = find_scene(c, scene);
   if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
@@ -1153,6 +1173,7 @@ int drt_cfr(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg,
 
 int drt_cfr_noalloc(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg,
                     const drt_freq_grid* fg, int32_t prec, void* H, void* stream) {
+  Range range_("drt_cfr_noalloc");
   if (!c) return fail(DRT_E_INVAL, "null context");
   Scene* s = find_scene(c, scene);
   if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
@@ -1180,6 +1201,7 @@ int drt_cfr_noalloc(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_g
 
 int drt_cfr_nufft(drt_ctx* c, uint32_t scene, int32_t n_rays, const drt_time_grid* tg, const drt_freq_grid* fg,
                   double eps, void* H, void* stream) {
+  Range range_("drt_cfr_nufft");
   if (!c) return fail(DRT_E_INVAL, "null context");
   Scene* s = find_scene(c, scene);
   if (!s) return fail(DRT_E_NOTFOUND, "scene %u", scene);
@@ -1253,6 +1275,7 @@ int drt_profile_read(drt_ctx* c, drt_profile* out, int reset) {
 }
 
 int drt_submit(drt_ctx* c, const drt_request* r, uint64_t* ticket) {
+  Range range_("drt_submit");
   if (!c || !r || !ticket) return fail(DRT_E_INVAL, "null argument");
   double now = drt_now_impl();
   int st;

@@ -500,25 +500,95 @@ __device__ __forceinline__ Split16 split_pair(float x, float y) {
 // hi + lo in binary16 and the product as hi.hi + hi.lo + lo.hi (three
 // v_mfma_f32_16x16x32_f16 per tile, relative error ~2^-22), accumulated in binary32.
 // One instruction contracts 32 slots = 16 rays x (re, im): lane l owns A[row l%16][slots
-// 8(l/16)..+7] and B[slots 8(l/16)..+7][column l%16], i.e. rays 4(l/16)..+3 of each block
-// of 16, and generates whole complex U and V values for them.  Each wave scales its ray
-// slice's gains by a power of two that puts the largest component near 2^13 (binary16
-// tops out at 65504 and is normal down to 2^-14) and divides it out of its accumulators
-// before the slices are summed.
-// Workgroup tile bid = (instant, ray group); red is the workgroup's LDS staging of waves 1..3.
-// Records reach their lanes through a per-wave LDS stage: each lane stores the record it
-// loaded, then the 16 lanes of a row read one record each (a broadcast read), which keeps the
-// hand-over off the vector ALU (DPP row broadcasts of the same words measured 4% slower).
+// 8(l/16) .. 8(l/16)+7] = rays 4(l/16) .. 4(l/16)+3 of the block, and B likewise.
+//
+// Operands come from per-ray phasor tables instead of one sine and cosine each.  With the
+// tile row or column m = 4a + b (0 <= a, b < 4),
+//   U[16 mt + m] = UA[a] UB[b] RU^mt,  UA[a] = |a| e^{-j 2 pi (phi0 + 4 a phiB)},
+//                                      UB[b] = e^{-j 2 pi b phiB},  RU = e^{-j 2 pi p16B},
+//   V[16 h + m]  = VA[a] VB[b] RV^h,   VA[a] = e^{j 2 pi 4 a phi1},  VB[b] = e^{j 2 pi b phi1},
+//                                      RV = e^{j 2 pi p16_1}
+// (V is stored as its conjugate, the (cos, sin) pair the C_re columns take).  Each lane builds
+// the tables of the ray it loaded (seven sine / cosine pairs, the rest products, the
+// products 4 phiB and 4 phi1 reduced in binary64) into LDS, and the lanes of the block take
+// one complex product per operand and one per further tile.
+struct PhTab {
+  float2 ua[4], ub[4], va[4], vb[4];
+  float4 rot;      // RU, RV
+};
+
+template <bool NEG>
+__device__ __forceinline__ float2 cis(float rev) {      // e^{-j 2 pi rev} if NEG, else e^{+j 2 pi rev}
+  const float c = __builtin_amdgcn_cosf(rev), s = __builtin_amdgcn_sinf(rev);
+  return float2{c, NEG ? -s : s};
+}
+__device__ __forceinline__ float2 cmul(float2 x, float2 y) {
+  return float2{__builtin_fmaf(x.x, y.x, -(x.y * y.y)), __builtin_fmaf(x.x, y.y, x.y * y.x)};
+}
+
+template <bool ROT_U, bool ROT_V>
+__device__ __forceinline__ void build_tab(const RecW& q, float kScale, PhTab& T) {
+  const double phiB = __builtin_bit_cast(double, q.w[2]), phi1 = __builtin_bit_cast(double, q.w[3]);
+  const float amp = __uint_as_float(uint32_t(q.w[0])) * kScale, phi0 = __uint_as_float(uint32_t(q.w[0] >> 32));
+  const float pB = __uint_as_float(uint32_t(q.w[1])), p1 = __uint_as_float(uint32_t(q.w[1] >> 32));
+  const float f4B = float(__builtin_amdgcn_fract(4.0 * phiB)), f41 = float(__builtin_amdgcn_fract(4.0 * phi1));
+  const float2 b1 = cis<true>(float(phiB)), e4 = cis<true>(f4B);
+  const float2 b2 = cmul(b1, b1), e8 = cmul(e4, e4);
+  float2 a0 = cis<true>(phi0);
+  a0 = float2{a0.x * amp, a0.y * amp};
+  const float2 a1 = cmul(a0, e4);
+  T.ua[0] = a0;
+  T.ua[1] = a1;
+  T.ua[2] = cmul(a0, e8);
+  T.ua[3] = cmul(a1, e8);
+  T.ub[0] = float2{1.f, 0.f};
+  T.ub[1] = b1;
+  T.ub[2] = b2;
+  T.ub[3] = cmul(b2, b1);
+  const float2 v1 = cis<false>(float(phi1)), f4 = cis<false>(f41);
+  const float2 v2 = cmul(v1, v1), f8 = cmul(f4, f4);
+  T.va[0] = float2{1.f, 0.f};
+  T.va[1] = f4;
+  T.va[2] = f8;
+  T.va[3] = cmul(f8, f4);
+  T.vb[0] = float2{1.f, 0.f};
+  T.vb[1] = v1;
+  T.vb[2] = v2;
+  T.vb[3] = cmul(v2, v1);
+  float2 ru{1.f, 0.f}, rv{1.f, 0.f};
+  if constexpr (ROT_U) ru = cis<true>(pB);
+  if constexpr (ROT_V) rv = cis<false>(p1);
+  T.rot = float4{ru.x, ru.y, rv.x, rv.y};
+}
+
+// LDS of one workgroup of the binary16 ray sum: each wave's phasor tables of its current 64
+// rays, and the partial tiles of waves 1-3 for the final sum.  Where the partial tiles fit
+// in the tables' space they share it (the tables are dead once every wave has left its loop).
+template <int MT, int NT> struct Cfr16Lds {
+  static constexpr bool kShare = sizeof(floatx4) * 3 * 64 * MT * NT <= sizeof(PhTab) * 4 * 64;
+  struct Split {
+    PhTab tab[4][64];
+    floatx4 red[3][64][MT * NT];
+  };
+  union Shared {
+    PhTab tab[4][64];
+    floatx4 red[3][64][MT * NT];
+  };
+  using type = typename std::conditional<kShare, Shared, Split>::type;
+};
+
 template <int MT, int NT>
 __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, float* out, int bid,
-                                           floatx4 (*red)[64][MT * NT], RecW (*stage)[64]) {
+                                           typename Cfr16Lds<MT, NT>::type& lds) {
   constexpr int B = 8 * NT;
+  constexpr bool ROT_U = MT > 1, ROT_V = (NT + 1) / 2 > 1;
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int g = bid % a.G, t = bid / a.G;
   int slice = g * 4 + wv;
   int r0 = slice * a.slice_len;
   int r1 = min(a.n_rays, r0 + a.slice_len);
   const int m = lane & 15, grp = lane >> 4;
+  const int ta = NT == 1 ? (m >> 2) & 1 : m >> 2, tb = m & 3;    // table indices of row / column m
   const RecM* rt = rec + size_t(t) * a.n_rays;
   floatx4 acc[MT][NT];
 #pragma unroll
@@ -526,9 +596,6 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  // lane 16 g + 4 b + j loads ray 16 b + 4 g + j of each batch of 64 (the same cache lines
-  // as a plain load): the four rays of block b that the lanes of row g consume then sit in
-  // row g, at positions 4 b .. 4 b + 3, and DPP row broadcasts hand them over without LDS
   const RecW* rw = reinterpret_cast<const RecW*>(rt);
   auto load = [&](int rb) {
     const int r = rb + lane;
@@ -542,12 +609,15 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
   (void)frexpf(amax, &e2);                       // amax < 2^e2
   const float kScale = amax > 0.f ? ldexpf(1.f, 13 - e2) : 1.f;
   const float kInv = 1.f / kScale;
+  PhTab (&tab)[64] = lds.tab[wv];
   RecW cur = load(r0);
   for (int rb = r0; rb < r1; rb += 64) {
-    // the wave's reads of the previous batch were issued before this store, and one wave's
-    // LDS operations complete in order
+    // the wave's reads of the previous batch's tables were issued before these stores, and
+    // one wave's LDS operations complete in order
+    PhTab mine;
+    build_tab<ROT_U, ROT_V>(cur, kScale, mine);      // rays past the slice have amplitude 0
     __builtin_amdgcn_wave_barrier();
-    stage[wv][lane] = cur;
+    tab[lane] = mine;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -557,28 +627,24 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
       constexpr int bk = decltype(BK)::value;
       if (bk >= nblk) return;
       // U operands of the 16 rays (lane: rays 4 grp .. 4 grp + 3 of the block) for every
-      // row tile; the V column phases' bases, kept for the column-tile loop below
+      // row tile, and the first column tile's V, kept for the column-tile loop below
       u32x4 ahw[MT], alw[MT];
-      float vb[4], vs[4];
+      float2 v0[4];
       static_for<0, 4>([&](auto J) {
         constexpr int j = decltype(J)::value;
-        const RecW q = stage[wv][16 * bk + 4 * grp + j];     // ray 16 bk + 4 grp + j of the batch
-        const uint64_t w0 = q.w[0], w1 = q.w[1], w2 = q.w[2], w3 = q.w[3];
-        const double phiB = __builtin_bit_cast(double, w2);
-        const double phi1 = __builtin_bit_cast(double, w3);
-        const float amp = __uint_as_float(uint32_t(w0)) * kScale, phi0 = __uint_as_float(uint32_t(w0 >> 32));
-        const float p16B = __uint_as_float(uint32_t(w1));
-        vs[j] = __uint_as_float(uint32_t(w1 >> 32));
-        const float u0 = row_phase(m, phiB, phi0);
+        const PhTab& T = tab[16 * bk + 4 * grp + j];     // ray 16 bk + 4 grp + j of the batch
+        float2 u = cmul(T.ua[ta], T.ub[tb]);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const float ph = mt == 0 ? u0 : __builtin_fmaf(float(mt), p16B, u0);
-          float sn = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
-          Split16 w = split_pair<false>(amp * c, -(amp * sn));   // U = |a| e^{-j 2 pi ph}
+          if (mt > 0) {
+            const float4 r = T.rot;
+            u = cmul(u, float2{r.x, r.y});
+          }
+          Split16 w = split_pair<false>(u.x, u.y);
           ahw[mt][j] = w.hi;
           alw[mt][j] = w.lo;
         }
-        vb[j] = float(__builtin_amdgcn_fract(double(NT == 1 ? (m & 7) : m) * phi1));
+        v0[j] = cmul(T.va[ta], T.vb[tb]);
       });
       half8 ah[MT], al[MT];
 #pragma unroll
@@ -593,8 +659,11 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
         u32x4 h0, l0, h1, l1;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float ph = hh == 0 ? vb[j] : __builtin_fmaf(float(hh), vs[j], vb[j]);
-          float sn = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);
+          if (hh > 0) {
+            const float4 r = tab[16 * bk + 4 * grp + j].rot;
+            v0[j] = cmul(v0[j], float2{r.z, r.w});
+          }
+          const float c = v0[j].x, sn = v0[j].y;
           if constexpr (NT == 1) {
             // C_re column: (V_re, -V_im) = (c, s); C_im column: (V_im, V_re) = (-s, c)
             Split16 w = (m >> 3) == 0 ? split_pair<false>(c, sn) : split_pair<false>(-sn, c);
@@ -633,11 +702,12 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
   for (int i = 0; i < MT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] *= kInv;      // exact: a power of two
+  if constexpr (Cfr16Lds<MT, NT>::kShare) __syncthreads();   // the tables die before the partial tiles land
   if (wv > 0) {
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
-      for (int j = 0; j < NT; ++j) red[wv - 1][lane][i * NT + j] = acc[i][j];
+      for (int j = 0; j < NT; ++j) lds.red[wv - 1][lane][i * NT + j] = acc[i][j];
   }
   __syncthreads();
   if (wv != 0) return;
@@ -646,7 +716,7 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
-      for (int j = 0; j < NT; ++j) acc[i][j] += red[w][lane][i * NT + j];
+      for (int j = 0; j < NT; ++j) acc[i][j] += lds.red[w][lane][i * NT + j];
   float* dst = out + (a.G > 1 ? size_t(g) * a.T * a.K * 2 : 0) + size_t(t) * a.K * 2;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -667,10 +737,9 @@ __device__ __forceinline__ void cfr16_tile(const RecM* rec, const CfrArgs& a, fl
 template <int MT, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT * NT <= 8 ? 4 : 1)))
 void k_cfr_mfma16(const RecM* rec, CfrArgs a, float* out) {
-  __shared__ floatx4 red[3][64][MT * NT];
-  __shared__ RecW stage[4][64];
+  __shared__ typename Cfr16Lds<MT, NT>::type lds;
   int bid = xcd_remap(blockIdx.x, gridDim.x);
-  if (bid < a.n_blocks) cfr16_tile<MT, NT>(rec, a, out, bid, red, stage);
+  if (bid < a.n_blocks) cfr16_tile<MT, NT>(rec, a, out, bid, lds);
 }
 
 template <class C>

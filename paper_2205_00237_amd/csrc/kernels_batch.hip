@@ -56,8 +56,7 @@ __global__ __launch_bounds__(256) void kb_geom(const BatchDesc* bd) {
 template <int MT, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT * NT <= 8 ? 4 : 1)))
 void kb_cfr16(const BatchDesc* bd) {
-  __shared__ floatx4 red[3][64][MT * NT];
-  __shared__ RecW stage[4][64];
+  __shared__ typename Cfr16Lds<MT, NT>::type lds;
   const int n = bd->n_req;
   const long long* off = bd->off[BK_CFR + (NT == 1 ? 0 : (NT == 2 ? 1 : (MT == 1 ? 2 : (MT == 2 ? 3 : 4))))];
   const long long it = blockIdx.x;
@@ -65,7 +64,7 @@ void kb_cfr16(const BatchDesc* bd) {
   const int j = __builtin_amdgcn_readfirstlane(req_of_uniform(off, n, it));
   const BatchReq& q = bd->req[j];
   const CfrArgs a = q.a;
-  cfr16_tile<MT, NT>((const RecM*)q.rec, a, a.G > 1 ? q.part : q.H, int(it - off[j]), red, stage);
+  cfr16_tile<MT, NT>((const RecM*)q.rec, a, a.G > 1 ? q.part : q.H, int(it - off[j]), lds);
 }
 
 __global__ __launch_bounds__(256) void kb_reduce(const BatchDesc* bd) {

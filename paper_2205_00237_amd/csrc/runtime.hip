@@ -490,7 +490,12 @@ static bool head_blocked(drt_ctx* c, Slot_& sl, Request* head, size_t need) {
 // Admit the queue head and, when it is batchable, the batchable requests behind it (FIFO)
 // while the batch has room, its work stays under the cap and its arena fits in the HBM
 // budget.  Returns false when the head has to wait for memory.
-static bool launch_next(drt_ctx* c, Slot_& sl) {
+// Admits the queue head (with what can batch behind it) to the free slot sl and launches it.
+// Called with c->mu held through lk; the lock is released while the batch is assembled and
+// launched (scratch growth, graph update, copies), so that callers of drt_submit and
+// drt_poll do not wait on the launch, and taken again before returning.  Only this thread
+// touches a slot that holds requests, and their scenes stay resident while they are in flight.
+static bool launch_next(drt_ctx* c, Slot_& sl, std::unique_lock<std::mutex>& lk) {
   Range range_("drt serving batch");
   Request* head = c->queue.front();
   CfrPlan hp;
@@ -533,6 +538,14 @@ static bool launch_next(drt_ctx* c, Slot_& sl) {
     c->inflight_bytes += q->footprint;
     sl.reqs.push_back(q);
   }
+  if (batch) {
+    c->stats.batches++;
+    c->stats.batched_requests += int(take.size());
+    if (int(take.size()) > c->stats.max_batch) c->stats.max_batch = int(take.size());
+  } else {
+    c->stats.single_launches++;
+  }
+  lk.unlock();
   int st = ensure_scratch(c, sl.scratch, arena, sl.stream, budget);
   if (st == DRT_OK && !batch) {
     Request* q = take[0].first;
@@ -544,7 +557,6 @@ static bool launch_next(drt_ctx* c, Slot_& sl) {
       st = run_cfr(nullptr, *q->scene, q->r.n_rays, &q->r.tg, &q->r.fg, q->r.precision, q->r.H, take[0].second,
                    sl.scratch.buf.p, sl.stream);
     }
-    c->stats.single_launches++;
   } else if (st == DRT_OK) {
     BatchDesc* h = sl.h_desc;
     const int n = int(take.size());
@@ -581,15 +593,11 @@ static bool launch_next(drt_ctx* c, Slot_& sl) {
     if (st == DRT_OK && (hipMemcpyAsync(sl.d_desc.p, h, bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
                          hipGraphLaunch(sl.exec, sl.stream) != hipSuccess))
       st = fail(DRT_E_DEVICE, "batch launch");
-    c->stats.batches++;
-    c->stats.batched_requests += n;
-    if (n > c->stats.max_batch) c->stats.max_batch = n;
   }
   if (st == DRT_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = DRT_E_DEVICE;
-  if (st != DRT_OK) {
-    (void)hipStreamSynchronize(sl.stream);
-    finish(c, sl, st);
-  }
+  if (st != DRT_OK) (void)hipStreamSynchronize(sl.stream);
+  lk.lock();
+  if (st != DRT_OK) finish(c, sl, st);
   return true;
 }
 
@@ -630,7 +638,7 @@ static void serve_loop(drt_ctx* c) {
           free_slot = &sl;
           break;
         }
-      if (!free_slot || !launch_next(c, *free_slot)) break;   // no slot, or waiting for memory
+      if (!free_slot || !launch_next(c, *free_slot, lk)) break;   // no slot, or waiting for memory
       progress = true;
     }
     bool busy = false;

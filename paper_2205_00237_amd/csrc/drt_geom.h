@@ -17,8 +17,36 @@ namespace drt {
 
 #define DRT_HD __host__ __device__ __forceinline__
 
-DRT_HD double msqrt(double x) { return ::sqrt(x); }
-DRT_HD float msqrt(float x) { return ::sqrtf(x); }
+// Square roots.  Device binary64: the library's own sequence (hardware reciprocal square
+// root, one Goldschmidt step on the root and its half-reciprocal, two residual corrections)
+// without its rescaling of inputs below 2^-767 and its special-value fix-up, so bitwise the
+// library's root for every argument the geometry forms (squared lengths: zero or far above
+// 2^-767).  Device binary32: the hardware root, within one ulp (the binary32 field
+// coefficients are held to 1e-5 relative), not the correctly rounded library sequence.
+// Host builds keep the library functions.
+DRT_HD double msqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  const double r = __builtin_fma(-h, s, 0.5);
+  s = __builtin_fma(s, r, s);
+  h = __builtin_fma(h, r, h);
+  double d = __builtin_fma(-s, s, x);
+  s = __builtin_fma(d, h, s);
+  d = __builtin_fma(-s, s, x);
+  s = __builtin_fma(d, h, s);
+  return x == 0.0 ? x : s;
+#else
+  return ::sqrt(x);
+#endif
+}
+DRT_HD float msqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_sqrtf(x);
+#else
+  return ::sqrtf(x);
+#endif
+}
 DRT_HD double mfloor(double x) { return ::floor(x); }
 DRT_HD float mfloor(float x) { return ::floorf(x); }
 DRT_HD double matan2(double y, double x) { return ::atan2(y, x); }

@@ -6,8 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdrt.so")
-SOURCES = ("kernels_geom.hip", "kernels_geom_more.hip", "kernels_cfr.hip", "kernels_batch.hip", "runtime.hip",
-           "trace.hip", "nufft.hip")
+SOURCES = ("kernels_geom.hip", "kernels_geom_more.hip", "kernels_cfr.hip", "kernels_batch.hip", "plan.hip",
+           "runtime.hip", "trace.hip", "nufft.hip")
 # test-only hardware probes (MFMA lane layouts, v_sin/v_cos): their own library under tests/
 PROBE_SRC = os.path.join(os.path.dirname(HERE), "tests", "probe", "probe.hip")
 PROBE_OUT = os.path.join(os.path.dirname(PROBE_SRC), "libdrt_probe.so")

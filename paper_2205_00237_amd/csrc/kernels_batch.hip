@@ -77,20 +77,6 @@ __global__ __launch_bounds__(256) void kb_reduce(const BatchDesc* bd) {
   reduce_item<float2>((const float2*)q.part, q.a.G, size_t(q.T) * q.a.K, (float2*)q.H, size_t(it - off[j]));
 }
 
-void batch_items(const BatchReq& q, long long items[BK_COUNT]) {
-  for (int k = 0; k < BK_COUNT; ++k) items[k] = 0;
-  items[BK_POSE] = (long long)q.sc.n_bodies * q.T;
-  for (int c = 0; c < CLS_COUNT; ++c) items[BK_GEOM + c] = (long long)((q.rc.count[c] + 3) / 4) * 4 * q.nchunk;
-  items[BK_CFR + cfr_shape(q.a.MT, q.a.NT)] = q.a.n_blocks;
-  if (q.a.G > 1) items[BK_REDUCE] = (long long)q.T * q.a.K;
-}
-
-long long batch_grid(int kind, long long items) {
-  if (items <= 0) return 1;
-  if (kind == BK_POSE || kind == BK_REDUCE) return (items + 255) / 256;   // a thread per item
-  if (kind < BK_CFR) return (items + 3) / 4;                              // a wave per item
-  return items;                                                           // a workgroup per item
-}
 
 void* batch_kernel(int kind) {
   switch (kind) {

@@ -28,57 +28,6 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-CfrArgs plan_cfr(int n_rays, int T, int K, double f0, double df, int target_waves, int prec, int split_path,
-                 int fp64_path) {
-  CfrArgs a{};
-  a.n_rays = n_rays;
-  a.T = T;
-  a.K = K;
-  a.f0 = f0;
-  a.df = df;
-  a.path = CFR_VALU;
-  const bool mfma64 = prec == DRT_FP64 && fp64_path == CFR_MFMA64 && K > 128 && K <= 1024;
-  if ((prec == DRT_SPLIT && K <= 2048 && split_path != CFR_VALU) || mfma64) {
-    a.path = mfma64 ? CFR_MFMA64 : split_path;
-    if (mfma64) {
-      a.NT = K > 512 ? 8 : (K > 256 ? 4 : 2);   // B = 8 NT: one row tile of K / B <= 16
-    } else {
-      a.NT = K <= 64 ? 1 : (K <= 256 ? 2 : 4);
-    }
-    a.B = 8 * a.NT;
-    a.K1 = (K + a.B - 1) / a.B;
-    a.MT = (a.K1 + 15) / 16;
-    if (a.MT == 3) a.MT = 4;
-    long tiles = T;
-    int G = int((target_waves + 4 * tiles - 1) / (4 * tiles));
-    int maxG = (n_rays + 4 * kMinSlice - 1) / (4 * kMinSlice);
-    if (G > maxG) G = maxG;
-    if (G < 1) G = 1;
-    a.G = G;
-    a.slice_len = (n_rays + 4 * G - 1) / (4 * G);
-    const int gran = a.path == CFR_MFMA16 ? 16 : 2;   // rays per matrix instruction
-    a.slice_len = (a.slice_len + gran - 1) / gran * gran;
-    a.n_blocks = int(tiles * G);
-    return a;
-  }
-  const int nk = nk_of(prec);
-  int blocks_k = (K + nk - 1) / nk;     // subcarrier blocks of nk
-  int kb = 1;
-  while (kb < blocks_k && kb < 64) kb <<= 1;
-  a.KB = kb;
-  a.TTc = 64 / kb;
-  a.nT = (T + a.TTc - 1) / a.TTc;
-  a.nK = (blocks_k + kb - 1) / kb;
-  long tiles = long(a.nT) * a.nK;
-  int G = int((target_waves + 4 * tiles - 1) / (4 * tiles));
-  int maxG = (n_rays + 4 * kMinSlice - 1) / (4 * kMinSlice);
-  if (G > maxG) G = maxG;
-  if (G < 1) G = 1;
-  a.G = G;
-  a.slice_len = (n_rays + 4 * G - 1) / (4 * G);
-  a.n_blocks = int(tiles * G);
-  return a;
-}
 
 hipError_t launch_cfr(const void* rec, const CfrArgs& a, int prec, void* out, hipStream_t st) {
   int grid = ((a.n_blocks + 7) / 8) * 8;

@@ -17,15 +17,6 @@ hipError_t launch_pose(const DBody* bodies, int nb, int T, double dt, int prec, 
   return hipGetLastError();
 }
 
-size_t pose_bytes(int nb, int T, int prec) {
-  return size_t(nb) * T * (prec == DRT_NAIVE32 ? sizeof(float2) : sizeof(double2));
-}
-
-size_t record_bytes(int n_rays, int T, int prec) {
-  size_t per = prec == DRT_FP64 ? std::max(sizeof(RecD), sizeof(RecM64))
-                                : (prec == DRT_SPLIT ? std::max(sizeof(RecS), sizeof(RecM)) : sizeof(RecN));
-  return size_t((T + 63) / 64) * n_rays * 64 * per;
-}
 
 hipError_t launch_geom_more(const SceneView& sc, const RayClasses& rc, const void* pose, int T, double dt,
                             double f_c, int n_rays, int prec, int mode, const ExtrapOut& eo, void* rec,

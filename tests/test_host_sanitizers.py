@@ -1,5 +1,6 @@
-"""Host code of the library built with AddressSanitizer and UndefinedBehaviorSanitizer (g++,
-host code only, every finding fatal):
+"""Host code of the library under the sanitizers, on the CPU.
+
+AddressSanitizer and UndefinedBehaviorSanitizer (g++, every finding fatal):
 
 * the shared device header's field functions (transition function, UTD coefficient,
   Fresnel, effective-roughness normalisation, the bounded binary32 sin/cos) over the input
@@ -12,7 +13,16 @@ host code only, every finding fatal):
   description, each with its error code.
 
 Every array the probe hands the loader is allocated at exactly its length, so a read past
-what the description holds is a sanitizer error."""
+what the description holds is a sanitizer error.
+
+ThreadSanitizer (clang's runtime, which intercepts the condition-variable waits of
+libstdc++): the runtime's host code, scheduler included, built against a host stand-in of the
+HIP API (tests/host/fake_hip: work completes at once, device memory is host memory, graph
+capture records its nodes) and driven by tests/host/serve_stress.cpp: three submitter
+threads, a poller, a direct drt_cfr / drt_extrapolate caller and the scheduler thread at once,
+the served results compared with drt_cfr, then a context destroyed with requests queued.
+Linked with the real ROCm runtime, the sanitizer's shadow mappings leave the runtime no GPU
+(it reports no device), hence the stand-in."""
 import math
 import os
 import shutil
@@ -275,3 +285,24 @@ def test_loader_rejections_clean_under_sanitizers(loader_probe):
     for (name, s, null, q, code), line in zip(cases, out):
         st, msg = _status(line)
         assert st == code, f"{name}: status {st} ({msg}), expected {code}"
+
+
+def test_scheduler_under_thread_sanitizer(tmp_path):
+    clang = "/opt/rocm/lib/llvm/bin/clang++"
+    if not os.path.exists(clang):
+        pytest.skip("clang++ not available")
+    exe = str(tmp_path / "serve_stress_tsan")
+    csrc = os.path.join(ROOT, "paper_2205_00237_amd", "csrc")
+    host = os.path.join(ROOT, "tests", "host")
+    cmd = [clang, "-O1", "-g", "-std=c++20", "-fsanitize=thread", "-fno-omit-frame-pointer",
+           "-I", os.path.join(host, "fake_hip"), "-I", os.path.join(ROOT, "include"), "-I", csrc,
+           "-idirafter", "/opt/rocm/include",
+           "-x", "c++", os.path.join(csrc, "runtime.hip"), "-x", "c++", os.path.join(csrc, "plan.hip"),
+           "-x", "c++", os.path.join(host, "fake_kernels.cpp"), "-x", "c++", os.path.join(host, "serve_stress.cpp"),
+           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib", "-lpthread", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 second_deadlock_stack=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert "ThreadSanitizer" not in r.stderr and r.returncode == 0, r.stderr[-4000:]
+    assert "served requests equal to drt_cfr" in r.stdout

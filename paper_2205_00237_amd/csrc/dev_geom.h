@@ -278,8 +278,21 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   }
 }
 
+// Waves per SIMD each geometry kernel is compiled for (1: as many as its registers allow).
+// Measured per class on the urban workload: the split ray-sum records gain from five waves
+// for reflection chains (96 registers, 60 B spilled) and three for chains with a diffraction
+// (168 registers, 116 B spilled), 9-11% each; drt_extrapolate's reflection kernel from
+// three (166 registers), 19%.  Its diffraction kernel and the binary64 kernels measured the
+// same or slower when squeezed, and keep their natural allocation.
+template <int MODE, int PREC, int CLS> constexpr int geom_waves() {
+  if (CLS == CLS_S) return 1;
+  if (MODE == GEOM_ANCHOR_MFMA && PREC == DRT_SPLIT) return CLS == CLS_R ? 5 : 3;
+  if ((MODE == GEOM_EXTRAP || MODE == GEOM_POWER) && PREC == DRT_SPLIT && CLS == CLS_R) return 3;
+  return 1;
+}
+
 template <class F, int MODE, int PREC, int CLS, bool POL>
-__global__ __launch_bounds__(256) void k_geom(SceneView sc, const int32_t* order, int count,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geom_waves<MODE, PREC, CLS>()))) void k_geom(SceneView sc, const int32_t* order, int count,
                                               const typename Vec2<F>::type* pose, int T, double dt, double f_c,
                                               int n_rays, int nchunk, ExtrapOut eo, void* rec, AnchorParams ap) {
   int wave = __builtin_amdgcn_readfirstlane(int(blockIdx.x) * 4 + int(threadIdx.x >> 6));

@@ -22,6 +22,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include <sys/prctl.h>
+
 #include "drt_geom.h"
 #include "drt_kernels.h"
 #include "scene_host.h"
@@ -604,6 +606,10 @@ static bool launch_next(drt_ctx* c, Slot_& sl, std::unique_lock<std::mutex>& lk)
 static void serve_loop(drt_ctx* c) {
   (void)hipSetDevice(c->device);
   roctxNameOsThread("drt serving loop");
+  // the loop sleeps 5 us between completion checks while batches run; the kernel's default
+  // timer slack (50 us) would stretch each of those sleeps, and with them the time from a
+  // batch's end to its requests reading done
+  (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
   std::unique_lock<std::mutex> lk(c->mu);
   while (true) {
     bool progress = false;
@@ -646,7 +652,7 @@ static void serve_loop(drt_ctx* c) {
     if (c->stop && c->queue.empty() && !busy) break;
     if (!progress) {
       if (busy)
-        c->cv.wait_for(lk, std::chrono::microseconds(20));
+        c->cv.wait_for(lk, std::chrono::microseconds(5));
       else
         c->cv.wait_for(lk, std::chrono::milliseconds(5));
     }

@@ -15,7 +15,8 @@ enum CfrPath { CFR_VALU = 0, CFR_MFMA = 1, CFR_MFMA16 = 2, CFR_MFMA64 = 3 };
 constexpr int kNK = 16;          // subcarriers walked by one lane from its phase anchor
 constexpr int kNK64 = 32;        // the same in binary64 (its phase anchor costs a binary64 sincos)
 inline int nk_of(int prec) { return prec == DRT_FP64 ? kNK64 : kNK; }
-constexpr int kMinSlice = 8;     // fewest rays per wave slice of the ray sum
+constexpr int kMinSlice = 64;    // fewest rays per wave slice of the ray sum (fewer ray groups, and no
+                                 // partial sums to reduce, for small calls)
 
 struct ExtrapOut {
   double* L;

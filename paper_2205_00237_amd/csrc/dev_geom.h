@@ -63,6 +63,18 @@ __device__ __forceinline__ void wave_bin_add(double* base, int key, double v, in
   if (key >= 0 && (lane == 63 || key != next)) unsafeAtomicAdd(base + key, v);
 }
 
+// A ray's record in registers, read as three 16-byte words.  Every lane reads the same
+// address, so these are scalar loads; the scalar unit has no byte loads, and reading the byte
+// fields one at a time would take a vector byte load and its full latency per field, each in
+// the dependent chain of the slot it selects.
+__device__ __forceinline__ DRay ray_regs(const DRay* rays, int r) {
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(rays + r);
+  struct Words { uint32_t w[12]; } w;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) w.w[i] = __builtin_amdgcn_readfirstlane(p[i]);   // whole words: no byte loads
+  return __builtin_bit_cast(DRay, w);
+}
+
 // One wave: ray order[i] over the 64 instants of chunk c, where wave = 4 (nchunk (i / 4) + c) + i % 4.
 template <class F, int MODE, int PREC, int CLS, bool POL = false>
 __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* order, int count,
@@ -78,7 +90,7 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   int t = chunk * 64 + lane;
   bool active = t < T;
   int tq = active ? t : T - 1;
-  const DRay& ray = sc.rays[r];
+  const DRay ray = ray_regs(sc.rays, r);
   if constexpr (MODE == GEOM_KIN) {
     // the chain as jets in time (binary64): points, velocities, accelerations, L'' (Sec.
     // III-A.1 eqs. ref_point_velo, ref_point_acc; App. B, C); the body angle's jet from the
@@ -90,14 +102,16 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
     const V3<J> TXj = ld3<J>(sc.tx_p) + tj * ld3<J>(sc.tx_v) + hj * ld3<J>(sc.tx_a);
     const V3<J> RXj = ld3<J>(sc.rx_p) + tj * ld3<J>(sc.rx_v) + hj * ld3<J>(sc.rx_a);
     Slot<J> sj[DRT_MAX_INT];
+    typename Vec2<double>::type pe[DRT_MAX_INT];
     const int nint = ray.nint;
+#pragma unroll
+    for (int i = 0; i < DRT_MAX_INT; ++i)
+      if (i < nint) pe[i] = pose[ray.body[i] * T + tq];
 #pragma unroll
     for (int i = 0; i < DRT_MAX_INT; ++i) {
       if (i < nint) {
-        const int b = ray.body[i];
-        const DBody& B = sc.bodies[b];
-        const auto pe = pose[b * T + tq];
-        const double sn = double(pe.x), c1 = double(pe.y), cs = 1.0 - c1;
+        const DBody& B = sc.bodies[ray.body[i]];
+        const double sn = double(pe[i].x), c1 = double(pe[i].y), cs = 1.0 - c1;
         const double w1 = B.w0 + B.wdot * tt, w2 = B.wdot;
         const J sth(sn, cs * w1, -sn * w1 * w1 + cs * w2), cth(c1, sn * w1, cs * w1 * w1 + sn * w2);
         load_slot<J>(sc, ray.kind[i], ray.prim[i], make_pose<J>(B, tj, sth, cth), sj[i]);
@@ -138,14 +152,18 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   V3<F> RX = ld3<F>(sc.rx_p) + dtj * ld3<F>(sc.rx_v) + half * ld3<F>(sc.rx_a);
   V3<F> VTX = ld3<F>(sc.tx_v) + dtj * ld3<F>(sc.tx_a);
   V3<F> VRX = ld3<F>(sc.rx_v) + dtj * ld3<F>(sc.rx_a);
+  // every slot's pose load issued before the first is used, so that their latencies overlap
   Slot<F> sl[DRT_MAX_INT];
-  int nint = ray.nint;
+  typename Vec2<F>::type pe[DRT_MAX_INT];
+  const int nint = ray.nint;
+#pragma unroll
+  for (int i = 0; i < DRT_MAX_INT; ++i)
+    if (i < nint) pe[i] = pose[ray.body[i] * T + tq];
 #pragma unroll
   for (int i = 0; i < DRT_MAX_INT; ++i) {
     if (i < nint) {
-      int b = ray.body[i];
-      auto pe = pose[b * T + tq];
-      Pose<F> ps = make_pose<F>(sc.bodies[b], dtj, F(pe.x), F(pe.y));
+      const int b = ray.body[i];
+      Pose<F> ps = make_pose<F>(sc.bodies[b], dtj, F(pe[i].x), F(pe[i].y));
       load_slot<F>(sc, ray.kind[i], ray.prim[i], ps, sl[i]);
     }
   }

@@ -63,18 +63,6 @@ __device__ __forceinline__ void wave_bin_add(double* base, int key, double v, in
   if (key >= 0 && (lane == 63 || key != next)) unsafeAtomicAdd(base + key, v);
 }
 
-// A ray's record in registers, read as three 16-byte words.  Every lane reads the same
-// address, so these are scalar loads; the scalar unit has no byte loads, and reading the byte
-// fields one at a time would take a vector byte load and its full latency per field, each in
-// the dependent chain of the slot it selects.
-__device__ __forceinline__ DRay ray_regs(const DRay* rays, int r) {
-  const uint32_t* p = reinterpret_cast<const uint32_t*>(rays + r);
-  struct Words { uint32_t w[12]; } w;
-#pragma unroll
-  for (int i = 0; i < 12; ++i) w.w[i] = __builtin_amdgcn_readfirstlane(p[i]);   // whole words: no byte loads
-  return __builtin_bit_cast(DRay, w);
-}
-
 // One wave: ray order[i] over the 64 instants of chunk c, where wave = 4 (nchunk (i / 4) + c) + i % 4.
 template <class F, int MODE, int PREC, int CLS, bool POL = false>
 __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* order, int count,
@@ -90,7 +78,7 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   int t = chunk * 64 + lane;
   bool active = t < T;
   int tq = active ? t : T - 1;
-  const DRay ray = ray_regs(sc.rays, r);
+  const DRay& ray = sc.rays[r];
   if constexpr (MODE == GEOM_KIN) {
     // the chain as jets in time (binary64): points, velocities, accelerations, L'' (Sec.
     // III-A.1 eqs. ref_point_velo, ref_point_acc; App. B, C); the body angle's jet from the
@@ -171,11 +159,14 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   using G = typename GainT<PREC>::type;
   // a slot's pose rebuilt where the Doppler and the monitor need it, from the instant and the
   // pose table; the empty asm statements keep the compiler from reusing (and so holding
-  // through the chain solve) the values computed when the slots were loaded
+  // through the chain solve) the values computed when the slots were loaded.  They are not
+  // volatile: a volatile one counts as a memory access, after which the scene tables are
+  // read by vector loads instead of scalar ones, and it keeps the rebuild alive in the
+  // record kernels, which never use the Doppler.
   auto pose_of = [&](int i) {
     F d = dtj;
     int at = ray.body[i] * T + tq;
-    asm volatile("" : "+v"(d), "+v"(at));
+    asm("" : "+v"(d), "+v"(at));
     const int b = ray.body[i];
     const auto pe = pose[at];
     return make_pose<F>(sc.bodies[b], d, F(pe.x), F(pe.y));

@@ -53,15 +53,14 @@ inline __host__ __device__ int sig_class(int code) {
   return code <= SIG_R4 ? CLS_R : (code == SIG_S ? CLS_S : CLS_D);
 }
 
-struct DRay {           // 48 B
-  uint8_t nint, code, dpos, pad;
-  uint8_t kind[4];
-  uint8_t pol[4];
+struct DRay {           // 80 B, whole words: a wave reads every field with a scalar load
+  int32_t nint, code, dpos, pad;
+  int32_t kind[4];
+  int32_t pol[4];
   int32_t prim[4];
   int32_t body[4];      // body of each slot's primitive (0 for unused slots)
-  int32_t pad2;
 };
-static_assert(sizeof(DRay) == 48, "DRay layout");
+static_assert(sizeof(DRay) == 80, "DRay layout");
 static_assert(sizeof(DBody) == 128, "DBody layout");
 
 struct SceneView {

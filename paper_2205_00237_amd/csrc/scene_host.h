@@ -76,7 +76,7 @@ static bool unit(const double* v) {
   return std::fabs(n - 1.0) < 1e-9;
 }
 
-static int sig_code(int nint, const uint8_t* kind, int* dpos) {
+template <class K> static int sig_code(int nint, const K* kind, int* dpos) {
   *dpos = 255;
   if (nint == 0) return SIG_LOS;
   if (kind[0] == DRT_S) return SIG_S;
@@ -228,8 +228,8 @@ static int validate_and_pack(const drt_scene_desc* d, PackedScene& s) {
       if (p < 0 || p >= lim) return fail(DRT_E_INVAL, "ray %d: primitive %d out of range", r, p);
       nd += k == DRT_D;
       ns += k == DRT_S;
-      R.kind[i] = uint8_t(k);
-      R.pol[i] = uint8_t(pol);
+      R.kind[i] = k;
+      R.pol[i] = pol;
       R.prim[i] = p;
       R.body[i] = k == DRT_R ? planes[p].body : k == DRT_D ? edges[p].body : tiles[p].body;
     }
@@ -237,10 +237,10 @@ static int validate_and_pack(const drt_scene_desc* d, PackedScene& s) {
       return fail(DRT_E_INVAL, "ray %d: two diffractions only as a two-edge ray, one diffraction otherwise", r);
     if (nd == 2 && R.prim[0] == R.prim[1]) return fail(DRT_E_INVAL, "ray %d: the two edges must differ", r);
     if (ns > 0 && n != 1) return fail(DRT_E_INVAL, "ray %d: scattering must be the only interaction", r);
-    R.nint = uint8_t(n);
+    R.nint = n;
     int dpos;
-    R.code = uint8_t(sig_code(n, R.kind, &dpos));
-    R.dpos = uint8_t(dpos);
+    R.code = sig_code(n, R.kind, &dpos);
+    R.dpos = dpos;
     s.cls_rays[sig_class(R.code)].push_back(r);
   }
 

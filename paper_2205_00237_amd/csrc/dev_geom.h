@@ -289,14 +289,16 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
 
 // Waves per SIMD each geometry kernel is compiled for (1: as many as its registers allow).
 // Measured per class on the urban workload: the split ray-sum records gain from five waves
-// for reflection chains (96 registers, 60 B spilled) and three for chains with a diffraction
-// (168 registers, 116 B spilled), 9-11% each; drt_extrapolate's reflection kernel from
-// three (166 registers), 19%.  Its diffraction kernel and the binary64 kernels measured the
-// same or slower when squeezed, and keep their natural allocation.
+// for reflection chains (96 registers) and three for chains with a diffraction (168), the
+// split drt_extrapolate kernels from four and three, the power profiles' reflection kernel
+// from four, and the binary64 record kernels with a diffraction from three.  The others
+// measured the same or slower when squeezed and keep their natural allocation.
 template <int MODE, int PREC, int CLS> constexpr int geom_waves() {
   if (CLS == CLS_S) return 1;
   if (MODE == GEOM_ANCHOR_MFMA && PREC == DRT_SPLIT) return CLS == CLS_R ? 5 : 3;
-  if ((MODE == GEOM_EXTRAP || MODE == GEOM_POWER) && PREC == DRT_SPLIT && CLS == CLS_R) return 3;
+  if (MODE == GEOM_EXTRAP && PREC == DRT_SPLIT) return CLS == CLS_R ? 4 : 3;
+  if (MODE == GEOM_POWER && PREC == DRT_SPLIT && CLS == CLS_R) return 4;
+  if ((MODE == GEOM_ANCHOR || MODE == GEOM_ANCHOR_MFMA) && PREC == DRT_FP64 && CLS == CLS_D) return 3;
   return 1;
 }
 

@@ -63,6 +63,13 @@ __device__ __forceinline__ void wave_bin_add(double* base, int key, double v, in
   if (key >= 0 && (lane == 63 || key != next)) unsafeAtomicAdd(base + key, v);
 }
 
+// Kind of slot i in the chains of signature (N, DP, SCAT): reflections, a diffraction at slot
+// DP (at both slots for DP = -2), or one scattering tile.  The loader derives the signature
+// code from the kinds, so this is the kind the ray record holds.
+template <int N, int DP, bool SCAT> constexpr int slot_kind(int i) {
+  return SCAT ? DRT_S : ((DP == -2 || i == DP) ? DRT_D : DRT_R);
+}
+
 // One wave: ray order[i] over the 64 instants of chunk c, where wave = 4 (nchunk (i / 4) + c) + i % 4.
 template <class F, int MODE, int PREC, int CLS, bool POL = false>
 __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* order, int count,
@@ -140,21 +147,6 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   V3<F> RX = ld3<F>(sc.rx_p) + dtj * ld3<F>(sc.rx_v) + half * ld3<F>(sc.rx_a);
   V3<F> VTX = ld3<F>(sc.tx_v) + dtj * ld3<F>(sc.tx_a);
   V3<F> VRX = ld3<F>(sc.rx_v) + dtj * ld3<F>(sc.rx_a);
-  // every slot's pose load issued before the first is used, so that their latencies overlap
-  Slot<F> sl[DRT_MAX_INT];
-  typename Vec2<F>::type pe[DRT_MAX_INT];
-  const int nint = ray.nint;
-#pragma unroll
-  for (int i = 0; i < DRT_MAX_INT; ++i)
-    if (i < nint) pe[i] = pose[ray.body[i] * T + tq];
-#pragma unroll
-  for (int i = 0; i < DRT_MAX_INT; ++i) {
-    if (i < nint) {
-      const int b = ray.body[i];
-      Pose<F> ps = make_pose<F>(sc.bodies[b], dtj, F(pe[i].x), F(pe[i].y));
-      load_slot<F>(sc, ray.kind[i], ray.prim[i], ps, sl[i]);
-    }
-  }
   F fc = F(f_c);
   using G = typename GainT<PREC>::type;
   // a slot's pose rebuilt where the Doppler and the monitor need it, from the instant and the
@@ -172,6 +164,17 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
     return make_pose<F>(sc.bodies[b], d, F(pe.x), F(pe.y));
   };
   RayResult<F, G> res = with_signature_in<F, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
+    // slots of a fixed signature: straight-line code, so that the loads of every slot (pose,
+    // body, primitive) go out together before the first is used
+    Slot<F> sl[N > 0 ? N : 1];
+    typename Vec2<F>::type pe[N > 0 ? N : 1];
+#pragma unroll
+    for (int i = 0; i < N; ++i) pe[i] = pose[ray.body[i] * T + tq];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      Pose<F> ps = make_pose<F>(sc.bodies[ray.body[i]], dtj, F(pe[i].x), F(pe[i].y));
+      load_slot<F>(sc, slot_kind<N, DP, SCAT>(i), ray.prim[i], ps, sl[i]);
+    }
     return eval_ray_with<F, G, N, DP, SCAT, false, MODE == GEOM_EXTRAP || MODE == GEOM_POWER, POL>(
         sc, ray, sl, TX, VTX, RX, VRX, fc, pose_of);
   });
@@ -288,17 +291,17 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
 }
 
 // Waves per SIMD each geometry kernel is compiled for (1: as many as its registers allow).
-// Measured per class on the urban workload: the split ray-sum records gain from five waves
-// for reflection chains (96 registers) and three for chains with a diffraction (168), the
-// split drt_extrapolate kernels from four and three, the power profiles' reflection kernel
-// from four, and the binary64 record kernels with a diffraction from three.  The others
-// measured the same or slower when squeezed and keep their natural allocation.
+// Measured per class on the urban workload: the split ray-sum records of reflection chains
+// gain from six waves (92 registers unconstrained), the split drt_extrapolate kernels from
+// four and three (146 and 169 unconstrained), the power profiles' diffraction kernel from
+// three, and the binary64 record kernels with a diffraction from four (158 unconstrained).
+// The others measured the same or slower when squeezed and keep their natural allocation.
 template <int MODE, int PREC, int CLS> constexpr int geom_waves() {
   if (CLS == CLS_S) return 1;
-  if (MODE == GEOM_ANCHOR_MFMA && PREC == DRT_SPLIT) return CLS == CLS_R ? 5 : 3;
+  if (MODE == GEOM_ANCHOR_MFMA && PREC == DRT_SPLIT && CLS == CLS_R) return 6;
   if (MODE == GEOM_EXTRAP && PREC == DRT_SPLIT) return CLS == CLS_R ? 4 : 3;
-  if (MODE == GEOM_POWER && PREC == DRT_SPLIT && CLS == CLS_R) return 4;
-  if ((MODE == GEOM_ANCHOR || MODE == GEOM_ANCHOR_MFMA) && PREC == DRT_FP64 && CLS == CLS_D) return 3;
+  if (MODE == GEOM_POWER && PREC == DRT_SPLIT && CLS == CLS_D) return 3;
+  if ((MODE == GEOM_ANCHOR || MODE == GEOM_ANCHOR_MFMA) && PREC == DRT_FP64 && CLS == CLS_D) return 4;
   return 1;
 }
 

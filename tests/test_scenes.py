@@ -50,7 +50,7 @@ def test_config5_request_stream():
 def test_config2_no_consecutive_coplanar_walls():
     s, _, _ = scenes.config2()
     for r in range(len(s["ray_nint"])):
-        n = s["ray_nint"][r]
+        n = int(s["ray_nint"][r])
         for i in range(n - 1):
             if i + 1 < n and s["ray_kind"][r, i] == s["ray_kind"][r, i + 1] == scenes.KIND_R:
                 p, q = s["ray_prim"][r, i], s["ray_prim"][r, i + 1]

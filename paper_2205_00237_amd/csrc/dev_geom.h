@@ -96,23 +96,21 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
     const J hj = J(0.5) * tj * tj;
     const V3<J> TXj = ld3<J>(sc.tx_p) + tj * ld3<J>(sc.tx_v) + hj * ld3<J>(sc.tx_a);
     const V3<J> RXj = ld3<J>(sc.rx_p) + tj * ld3<J>(sc.rx_v) + hj * ld3<J>(sc.rx_a);
-    Slot<J> sj[DRT_MAX_INT];
-    typename Vec2<double>::type pe[DRT_MAX_INT];
     const int nint = ray.nint;
+    KinResult<J> kr = with_signature_in<J, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
+      // as below: slots of a fixed signature, loaded in straight-line code
+      Slot<J> sj[N > 0 ? N : 1];
+      typename Vec2<double>::type pe[N > 0 ? N : 1];
 #pragma unroll
-    for (int i = 0; i < DRT_MAX_INT; ++i)
-      if (i < nint) pe[i] = pose[ray.body[i] * T + tq];
+      for (int i = 0; i < N; ++i) pe[i] = pose[ray.body[i] * T + tq];
 #pragma unroll
-    for (int i = 0; i < DRT_MAX_INT; ++i) {
-      if (i < nint) {
+      for (int i = 0; i < N; ++i) {
         const DBody& B = sc.bodies[ray.body[i]];
         const double sn = double(pe[i].x), c1 = double(pe[i].y), cs = 1.0 - c1;
         const double w1 = B.w0 + B.wdot * tt, w2 = B.wdot;
         const J sth(sn, cs * w1, -sn * w1 * w1 + cs * w2), cth(c1, sn * w1, cs * w1 * w1 + sn * w2);
-        load_slot<J>(sc, ray.kind[i], ray.prim[i], make_pose<J>(B, tj, sth, cth), sj[i]);
+        load_slot<J>(sc, slot_kind<N, DP, SCAT>(i), ray.prim[i], make_pose<J>(B, tj, sth, cth), sj[i]);
       }
-    }
-    KinResult<J> kr = with_signature_in<J, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
       return kin_ray<J, N, DP, SCAT>(sj, TXj, RXj);
     });
     if (!active) return;

@@ -213,14 +213,17 @@ static void free_scene(drt_ctx* c, Scene& s) {
   dev_free(c, s.d_order);
 }
 
-// The rays [0, n_rays) of each signature class for one call.
+// The rays [0, n_rays) of each signature class for one call: the signature-sorted lists
+// (second half of d_order) when the call covers every ray of the scene, else the prefix of
+// the ascending lists (first half).
 static RayClasses classes(const Scene& s, int n_rays) {
   RayClasses rc{};
-  size_t off = 0;
+  const bool all = size_t(n_rays) >= s.rays.size();
+  size_t off = all ? s.rays.size() : 0;
   for (int c = 0; c < CLS_COUNT; ++c) {
     const auto& v = s.cls_rays[c];
     rc.order[c] = (const int32_t*)s.d_order.p + off;
-    rc.count[c] = int(std::lower_bound(v.begin(), v.end(), n_rays) - v.begin());
+    rc.count[c] = all ? int(v.size()) : int(std::lower_bound(v.begin(), v.end(), n_rays) - v.begin());
     off += v.size();
   }
   return rc;
@@ -764,8 +767,9 @@ static int make_resident(drt_ctx* c, std::unique_ptr<Scene> s, uint32_t* id) {
     free_scene(c, *s);
     return st;
   }
-  std::vector<int32_t> order;
+  std::vector<int32_t> order;    // ascending class lists, then the signature-sorted ones
   for (int k = 0; k < CLS_COUNT; ++k) order.insert(order.end(), s->cls_rays[k].begin(), s->cls_rays[k].end());
+  for (int k = 0; k < CLS_COUNT; ++k) order.insert(order.end(), s->cls_by_sig[k].begin(), s->cls_by_sig[k].end());
   if ((st = upload(c, s->d_order, order.data(), order.size()))) {
     free_scene(c, *s);
     return st;

@@ -66,6 +66,9 @@ struct PackedScene {
   std::vector<DTile> tiles;
   std::vector<DRay> rays;
   std::vector<int32_t> cls_rays[CLS_COUNT];   // ray indices of each signature class, ascending
+  // the same lists stable-sorted by signature code: a call over every ray of the scene walks
+  // each class signature by signature, so that neighbouring waves run the same code
+  std::vector<int32_t> cls_by_sig[CLS_COUNT];
 };
 
 // ---------------------------------------------------------------------------------------
@@ -242,6 +245,11 @@ static int validate_and_pack(const drt_scene_desc* d, PackedScene& s) {
     R.code = sig_code(n, R.kind, &dpos);
     R.dpos = dpos;
     s.cls_rays[sig_class(R.code)].push_back(r);
+  }
+  for (int c = 0; c < CLS_COUNT; ++c) {
+    s.cls_by_sig[c] = s.cls_rays[c];
+    std::stable_sort(s.cls_by_sig[c].begin(), s.cls_by_sig[c].end(),
+                     [&](int32_t a, int32_t b) { return s.rays[a].code < s.rays[b].code; });
   }
 
   // host view for the t0 checks

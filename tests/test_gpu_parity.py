@@ -128,6 +128,30 @@ def test_ragged_shapes(ctx, T, K, nr):
     ctx.unload_scene(sid)
 
 
+def test_whole_scene_and_prefix_calls_agree(ctx):
+    """A call over every ray walks the signature-sorted class lists, a call over a prefix the
+    ascending ones; each (ray, instant) is computed the same either way, so the outputs and H
+    of the common rays are bitwise equal (urban scene: interleaved diffraction signatures)."""
+    say("whole-scene vs prefix calls, urban scene, 100 instants")
+    s, _, fg = scenes.config2()
+    tg = scenes.TimeGrid(5e-4, 100)
+    fgs = scenes.FreqGrid(fg.f_c, fg.bandwidth / 8, 128)
+    sid = ctx.load_scene(s)
+    R = len(s["ray_nint"])
+    for prec in (0, 1):
+        a = ctx.extrapolate(sid, tg, fg.f_c, prec)
+        b = ctx.extrapolate(sid, tg, fg.f_c, prec, n_rays=R - 1)
+        for k in ("L", "dop", "aod_az", "aoa_el", "gain", "valid", "in_bounds"):
+            assert torch.equal(a[k][: R - 1], b[k]), (prec, k)
+        # H of the prefix call against a whole-scene call on the scene of those rays alone
+        Ha = ctx.cfr(sid, tg, fgs, prec, n_rays=R - 1).cpu().numpy()
+        sid1 = ctx.load_scene(scenes.subset_rays(s, np.arange(R - 1)))
+        Hb = ctx.cfr(sid1, tg, fgs, prec).cpu().numpy()
+        ctx.unload_scene(sid1)
+        assert np.array_equal(Ha, Hb), prec
+    ctx.unload_scene(sid)
+
+
 def test_empty_inputs(ctx):
     say("empty inputs")
     s, tg, fg = scenes.config1()

@@ -22,14 +22,30 @@ template <> struct Vec2<float> { using type = float2; };
 
 // ---------------------------------------------------------------------------------------
 
+// (sin theta, 1 - cos theta) of body B at instant j.  Not inlined, so that the pose table
+// and the geometry waves that compute a pose in place (small merged launches) run the same
+// machine code and agree bit for bit.
+template <class F>
+__device__ __noinline__ typename Vec2<F>::type pose_value(const DBody& B, int j, double dt) {
+  F d = F(double(j) * dt);
+  F th = F(B.w0) * d + F(0.5) * F(B.wdot) * d * d;
+  F h = msin(th * F(0.5));
+  return {msin(th), F(2) * h * h};   // 1 - cos(theta) without cancellation
+}
+
 template <class F>
 __device__ __forceinline__ void pose_item(const DBody* bodies, int T, double dt, int i,
                                           typename Vec2<F>::type* out) {
   int b = i / T, j = i - b * T;
-  F d = F(double(j) * dt);
-  F th = F(bodies[b].w0) * d + F(0.5) * F(bodies[b].wdot) * d * d;
-  F h = msin(th * F(0.5));
-  out[i] = {msin(th), F(2) * h * h};   // 1 - cos(theta) without cancellation
+  out[i] = pose_value<F>(bodies[b], j, dt);
+}
+
+// The pose of body b at instant j, from the table or computed in place.
+template <class F, bool INLINE>
+__device__ __forceinline__ typename Vec2<F>::type pose_at(const typename Vec2<F>::type* pose, const DBody* bodies,
+                                                          int b, int T, int j, double dt) {
+  if constexpr (INLINE) return pose_value<F>(bodies[b], j, dt);
+  else return pose[b * T + j];
 }
 
 template <class F>
@@ -71,7 +87,7 @@ template <int N, int DP, bool SCAT> constexpr int slot_kind(int i) {
 }
 
 // One wave: ray order[i] over the 64 instants of chunk c, where wave = 4 (nchunk (i / 4) + c) + i % 4.
-template <class F, int MODE, int PREC, int CLS, bool POL = false>
+template <class F, int MODE, int PREC, int CLS, bool POL = false, bool INLINE_POSE = false>
 __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* order, int count,
                                           const typename Vec2<F>::type* pose, int T, double dt, double f_c,
                                           int n_rays, int nchunk, const ExtrapOut& eo, void* rec,
@@ -155,10 +171,10 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
   // record kernels, which never use the Doppler.
   auto pose_of = [&](int i) {
     F d = dtj;
-    int at = ray.body[i] * T + tq;
-    asm("" : "+v"(d), "+v"(at));
+    int j = tq;
+    asm("" : "+v"(d), "+v"(j));
     const int b = ray.body[i];
-    const auto pe = pose[at];
+    const auto pe = pose_at<F, INLINE_POSE>(pose, sc.bodies, b, T, j, dt);
     return make_pose<F>(sc.bodies[b], d, F(pe.x), F(pe.y));
   };
   RayResult<F, G> res = with_signature_in<F, CLS>(ray.code, [&]<int N, int DP, bool SCAT>() {
@@ -167,7 +183,7 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
     Slot<F> sl[N > 0 ? N : 1];
     typename Vec2<F>::type pe[N > 0 ? N : 1];
 #pragma unroll
-    for (int i = 0; i < N; ++i) pe[i] = pose[ray.body[i] * T + tq];
+    for (int i = 0; i < N; ++i) pe[i] = pose_at<F, INLINE_POSE>(pose, sc.bodies, ray.body[i], T, tq, dt);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       Pose<F> ps = make_pose<F>(sc.bodies[ray.body[i]], dtj, F(pe[i].x), F(pe[i].y));
@@ -312,6 +328,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(geom_waves<
                                      int(threadIdx.x & 63));
 }
 
+
+// The geometry of every signature class in one launch (small calls of the ray-sum record
+// modes): workgroups [0, wR) take the reflection class, then the diffraction class, then
+// scattering; class boundaries fall on workgroups, so each workgroup runs one class's code.
+// Poses are computed in place (pose_value), so such a call needs no pose-table kernel.
+template <class F, int MODE, int PREC, bool POL>
+__global__ __launch_bounds__(256) void k_geom_merged(SceneView sc, RayClasses rc, const typename Vec2<F>::type* pose,
+                                                     int T, double dt, double f_c, int n_rays, int nchunk,
+                                                     ExtrapOut eo, void* rec, AnchorParams ap) {
+  const int wg = int(blockIdx.x), lane = int(threadIdx.x & 63);
+  const int gR = class_workgroups(rc, CLS_R, T), gD = class_workgroups(rc, CLS_D, T);
+  const int w = int(threadIdx.x >> 6);
+  if (wg < gR) {
+    geom_wave<F, MODE, PREC, CLS_R, POL, true>(sc, rc.order[CLS_R], rc.count[CLS_R], pose, T, dt, f_c, n_rays, nchunk, eo,
+                                         rec, ap, __builtin_amdgcn_readfirstlane(wg * 4 + w), lane);
+  } else if (wg < gR + gD) {
+    geom_wave<F, MODE, PREC, CLS_D, POL, true>(sc, rc.order[CLS_D], rc.count[CLS_D], pose, T, dt, f_c, n_rays, nchunk, eo,
+                                         rec, ap, __builtin_amdgcn_readfirstlane((wg - gR) * 4 + w), lane);
+  } else {
+    geom_wave<F, MODE, PREC, CLS_S, POL, true>(sc, rc.order[CLS_S], rc.count[CLS_S], pose, T, dt, f_c, n_rays, nchunk, eo,
+                                         rec, ap, __builtin_amdgcn_readfirstlane((wg - gR - gD) * 4 + w), lane);
+  }
+}
 
 }  // namespace drt
 

@@ -13,6 +13,16 @@ static void launch_classes(const SceneView& sc, const RayClasses& rc, const void
                            hipStream_t st) {
   using P = const typename Vec2<F>::type*;
   int nchunk = (T + 63) / 64;
+  if constexpr (MODE == GEOM_ANCHOR || MODE == GEOM_ANCHOR_MFMA) {
+    if (geom_merged(rc, T)) {
+      int n = 0;
+      for (int c = 0; c < CLS_COUNT; ++c) n += class_workgroups(rc, c, T);
+      if (n > 0)
+        hipLaunchKernelGGL((k_geom_merged<F, MODE, PREC, POL>), dim3(unsigned(n)), dim3(256), 0, st, sc, rc, (P)pose,
+                           T, dt, f_c, n_rays, nchunk, eo, rec, ap);
+      return;
+    }
+  }
   for (int c = 0; c < CLS_COUNT; ++c) {
     if (rc.count[c] == 0) continue;
     dim3 grid(unsigned(long((rc.count[c] + 3) / 4) * nchunk));   // 4 rays x 64 instants per workgroup

@@ -51,11 +51,23 @@ struct AnchorParams {
   double f1c;   // df / c: phase step between adjacent subcarriers
 };
 
-// Rays of each signature class (indices into the scene's ray table, ascending) for one call.
+// Rays of each signature class (indices into the scene's ray table) for one call.
 struct RayClasses {
   const int32_t* order[CLS_COUNT];
   int count[CLS_COUNT];
 };
+
+// Geometry workgroups of one class (4 rays x 64 instants each).
+__host__ __device__ inline int class_workgroups(const RayClasses& rc, int c, int T) { return (rc.count[c] + 3) / 4 * ((T + 63) / 64); }
+
+// Ray-sum record geometry of a small call runs as one kernel over every class (each workgroup
+// takes its class's path) instead of one kernel per class: launches, not work, set its time.
+constexpr int kMergedGeomMax = 256;   // most workgroups of a merged launch
+inline bool geom_merged(const RayClasses& rc, int T) {
+  int n = 0;
+  for (int c = 0; c < CLS_COUNT; ++c) n += class_workgroups(rc, c, T);
+  return n <= kMergedGeomMax;
+}
 
 // ---------------------------------------------------------------------------------------
 // Batched serving.  A batch is up to kMaxBatch split-precision requests whose ray sum runs

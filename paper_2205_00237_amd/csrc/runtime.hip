@@ -229,11 +229,12 @@ static RayClasses classes(const Scene& s, int n_rays) {
   return rc;
 }
 
-// geometry kernels one launch makes (one per non-empty signature class)
-static int class_kernels(const RayClasses& rc, int T) {
+// geometry kernels one launch makes (one per non-empty signature class, or one merged kernel
+// for a small ray-sum call)
+static int class_kernels(const RayClasses& rc, int T, bool ray_sum = false) {
   int n = 0;
   for (int c = 0; c < CLS_COUNT; ++c) n += rc.count[c] > 0 && T > 0;
-  return n;
+  return ray_sum && n > 0 && geom_merged(rc, T) ? 1 : n;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -298,18 +299,20 @@ static int run_cfr(drt_ctx* c, const Scene& s, int n_rays, const drt_time_grid* 
                    int prec, void* H, const CfrPlan& p, void* scratch, hipStream_t st) {
   char* base = (char*)scratch;
   int T = tg->n_steps;
-  HIP_OK(timed(c, DRT_K_POSE, st, [&] {
-    return launch_pose((const DBody*)s.d_bodies.p, s.view.n_bodies, T, tg->dt, prec, base + p.pose_off, st);
-  }));
+  const RayClasses rc = classes(s, n_rays);
+  if (!geom_merged(rc, T)) {   // a merged geometry launch computes its poses in place
+    HIP_OK(timed(c, DRT_K_POSE, st, [&] {
+      return launch_pose((const DBody*)s.d_bodies.p, s.view.n_bodies, T, tg->dt, prec, base + p.pose_off, st);
+    }));
+  }
   ExtrapOut none{};
   const double inv_c = 1.0 / 299792458.0;
   AnchorParams ap{p.a.f0 * inv_c, double(p.a.B) * p.a.df * inv_c, p.a.df * inv_c};
   int mode = p.a.path == CFR_VALU ? GEOM_ANCHOR : GEOM_ANCHOR_MFMA;
-  const RayClasses rc = classes(s, n_rays);
   HIP_OK(timed(c, DRT_K_GEOM, st, [&] {
     return launch_geom(device_view(s), rc, base + p.pose_off, T, tg->dt, fg->f_c, n_rays, prec,
                        mode, none, base + p.rec_off, ap, st);
-  }, class_kernels(rc, T)));
+  }, class_kernels(rc, T, true)));
   if (p.a.G > 1) {
     HIP_OK(timed(c, DRT_K_CFR, st, [&] { return launch_cfr(base + p.rec_off, p.a, prec, base + p.part_off, st); }));
     HIP_OK(timed(c, DRT_K_REDUCE, st, [&] {

@@ -341,14 +341,14 @@ __global__ __launch_bounds__(256) void k_geom_merged(SceneView sc, RayClasses rc
   const int gR = class_workgroups(rc, CLS_R, T), gD = class_workgroups(rc, CLS_D, T);
   const int w = int(threadIdx.x >> 6);
   if (wg < gR) {
-    geom_wave<F, MODE, PREC, CLS_R, POL, true>(sc, rc.order[CLS_R], rc.count[CLS_R], pose, T, dt, f_c, n_rays, nchunk, eo,
-                                         rec, ap, __builtin_amdgcn_readfirstlane(wg * 4 + w), lane);
+    geom_wave<F, MODE, PREC, CLS_R, POL, true>(sc, rc.order[CLS_R], rc.count[CLS_R], pose, T, dt, f_c, n_rays,
+                                               nchunk, eo, rec, ap, __builtin_amdgcn_readfirstlane(wg * 4 + w), lane);
   } else if (wg < gR + gD) {
-    geom_wave<F, MODE, PREC, CLS_D, POL, true>(sc, rc.order[CLS_D], rc.count[CLS_D], pose, T, dt, f_c, n_rays, nchunk, eo,
-                                         rec, ap, __builtin_amdgcn_readfirstlane((wg - gR) * 4 + w), lane);
+    geom_wave<F, MODE, PREC, CLS_D, POL, true>(sc, rc.order[CLS_D], rc.count[CLS_D], pose, T, dt, f_c, n_rays,
+                                               nchunk, eo, rec, ap, __builtin_amdgcn_readfirstlane((wg - gR) * 4 + w), lane);
   } else {
-    geom_wave<F, MODE, PREC, CLS_S, POL, true>(sc, rc.order[CLS_S], rc.count[CLS_S], pose, T, dt, f_c, n_rays, nchunk, eo,
-                                         rec, ap, __builtin_amdgcn_readfirstlane((wg - gR - gD) * 4 + w), lane);
+    geom_wave<F, MODE, PREC, CLS_S, POL, true>(sc, rc.order[CLS_S], rc.count[CLS_S], pose, T, dt, f_c, n_rays,
+                                               nchunk, eo, rec, ap, __builtin_amdgcn_readfirstlane((wg - gR - gD) * 4 + w), lane);
   }
 }
 

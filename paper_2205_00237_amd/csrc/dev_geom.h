@@ -129,30 +129,42 @@ __device__ __forceinline__ void geom_wave(const SceneView& sc, const int32_t* or
       }
       return kin_ray<J, N, DP, SCAT>(sj, TXj, RXj);
     });
-    if (!active) return;
     const size_t o = size_t(r) * T + t;
-    if (eo.dop_rate) eo.dop_rate[o] = kr.ok ? float(-(f_c / 299792458.0) * kr.L.dd) : 0.f;
+    if (active && eo.dop_rate) eo.dop_rate[o] = kr.ok ? float(-(f_c / 299792458.0) * kr.L.dd) : 0.f;
+    // One quantity's 12 values per lane are contiguous in [ray][instant][slot][xyz], so the
+    // wave's 64 instants span 6 KB: staged in LDS and written as 16-byte pieces at consecutive
+    // addresses, instead of one 24-byte run per lane with the lanes 96 bytes apart.
+    constexpr int kPer = DRT_MAX_INT * 3;
+    __shared__ double stage[4][64 * kPer];
+    double* sw = stage[threadIdx.x >> 6];
+    const int nd = max(0, min(64, T - chunk * 64)) * kPer;     // values of the active instants
+    const size_t base = (size_t(r) * T + size_t(chunk) * 64) * kPer;
+    auto put = [&](double* dst, int which) {
+      if (!dst) return;
 #pragma unroll
-    for (int i = 0; i < DRT_MAX_INT; ++i) {
-      const bool w = kr.ok && i < nint;
-      const V3<J> q = kr.Q[i];
-      const size_t e = (o * DRT_MAX_INT + i) * 3;
-      if (eo.q_pos) {
-        eo.q_pos[e] = w ? q.x.v : 0.0;
-        eo.q_pos[e + 1] = w ? q.y.v : 0.0;
-        eo.q_pos[e + 2] = w ? q.z.v : 0.0;
+      for (int i = 0; i < DRT_MAX_INT; ++i) {
+        const bool w = kr.ok && i < nint;
+        const V3<J> q = kr.Q[i];
+        const double x = which == 0 ? q.x.v : which == 1 ? q.x.d : q.x.dd;
+        const double y = which == 0 ? q.y.v : which == 1 ? q.y.d : q.y.dd;
+        const double z = which == 0 ? q.z.v : which == 1 ? q.z.d : q.z.dd;
+        sw[lane * kPer + 3 * i] = w ? x : 0.0;
+        sw[lane * kPer + 3 * i + 1] = w ? y : 0.0;
+        sw[lane * kPer + 3 * i + 2] = w ? z : 0.0;
       }
-      if (eo.q_vel) {
-        eo.q_vel[e] = w ? q.x.d : 0.0;
-        eo.q_vel[e + 1] = w ? q.y.d : 0.0;
-        eo.q_vel[e + 2] = w ? q.z.d : 0.0;
-      }
-      if (eo.q_acc) {
-        eo.q_acc[e] = w ? q.x.dd : 0.0;
-        eo.q_acc[e + 1] = w ? q.y.dd : 0.0;
-        eo.q_acc[e + 2] = w ? q.z.dd : 0.0;
-      }
-    }
+      // one wave's LDS operations complete in order
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int c = 2 * lane; c < nd; c += 128)
+        *reinterpret_cast<double2*>(dst + base + c) = *reinterpret_cast<const double2*>(sw + c);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    put(eo.q_pos, 0);
+    put(eo.q_vel, 1);
+    put(eo.q_acc, 2);
     return;
   }
   F dtj = F(double(tq) * dt);
